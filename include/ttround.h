@@ -1,0 +1,166 @@
+/*
+ * ttround.h -- C ABI of libttround.so: KRP-sketched randomized TT-rounding
+ * on AMD Instinct MI355X (gfx950).
+ *
+ * Method: Al Daas, Ballard, Grigori, Martinez Aguilar, Saibaba, Verma,
+ * "Adaptive Randomized Tensor Train Rounding using Khatri-Rao Products"
+ * (arXiv 2511.03598).  Section numbers below refer to that paper.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - A TT tensor has d >= 2 cores X_k of shape (r_{k-1}, n_k, r_k) with
+ *    r_0 = r_d = 1 (Sec. 2.2).  Cores are float64, row-major, so element
+ *    (a, i, b) of core k sits at offset (a*n_k + i)*r_k + b; the vertical
+ *    unfolding V(X_k) and horizontal unfolding H(X_k) are plain views.
+ *  - Core and output pointers are DEVICE pointers on the current HIP
+ *    device; the arrays that hold them, and dims/ranks, are HOST arrays.
+ *  - Inputs are borrowed: they must stay valid and unmodified until the
+ *    call returns (synchronous calls) or until tt_round_poll reports the
+ *    request done (served calls).  The library never frees caller memory.
+ *  - Work is enqueued on opts->stream (a hipStream_t; NULL = the null
+ *    stream).  Synchronous entry points return after the result is complete
+ *    on that stream (they synchronize it), so outputs are ready on return.
+ *  - Errors are status codes; no exception crosses the ABI.  A thread-local
+ *    message is available from tt_last_error().  On error the outputs are
+ *    unspecified but no caller memory outside the outputs is written.
+ *  - Determinism: the same inputs, seed and options give bitwise-identical
+ *    outputs (fixed-order reductions, no floating-point atomics).
+ *  - Threads: calls from different host threads are safe; calls that share
+ *    a stream are serialized by it.
+ *
+ * Gaussian mode factors (Sec. 3.2, "Select random Gaussian matrices").  The
+ * paper leaves the generator open; this library fixes Philox4x32-10
+ * (Salmon et al., SC'11) with key (seed & 0xffffffff, seed >> 32) and
+ * counter (p, c, j, 0x4B525031) for row pair p, global sketch column c and
+ * 1-based mode j, and Box-Muller on two 53-bit uniforms
+ * u = ((w_hi*2^32 + w_lo) >> 11) + 0.5) * 2^-53:
+ *   Omega_j(2p, c)   = sqrt(-2 ln u1) cos(2 pi u2)
+ *   Omega_j(2p+1, c) = sqrt(-2 ln u1) sin(2 pi u2).
+ * Every entry is addressed by (seed, j, c, row), so a sketch column is the
+ * same whichever pass or chunk generates it.
+ */
+#ifndef TTROUND_H
+#define TTROUND_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    TT_OK = 0,
+    TT_PENDING = 1,       /* served request not finished yet               */
+    TT_EINVAL = -1,       /* bad argument (shape, rank, tol, pointer)      */
+    TT_ENOMEM = -2,       /* output capacity too small or allocation failed */
+    TT_ECAPACITY = -3,    /* admission refused (server budget)             */
+    TT_EDEVICE = -4,      /* a HIP runtime error                           */
+    TT_ENOTFOUND = -5,    /* unknown ticket                                */
+    TT_EUNSUPPORTED = -6  /* valid request outside the implemented limits  */
+} tt_status;
+
+/* Precision of the right-to-left partial contractions (the KRP sketch,
+ * Sec. 3.1) only; the sketch, QR, projection, estimator and recompression
+ * steps always run in float64.  Reduced precisions keep a power-of-two
+ * exponent per sketch column in int32 so that values stay in range. */
+typedef enum { TT_PREC_F64 = 0, TT_PREC_F32 = 1, TT_PREC_BF16 = 2 } tt_prec;
+
+typedef struct {
+    int32_t d;                  /* number of cores, >= 2                    */
+    const int64_t* n;           /* host [d], n_k >= 1                       */
+    const int64_t* ranks;       /* host [d+1], ranks[0] = ranks[d] = 1      */
+    const double* const* cores; /* host [d] device pointers, see above      */
+} tt_view;
+
+typedef struct {
+    int32_t d;                  /* must equal the input's d                 */
+    int64_t* ranks;             /* host [d+1], written by the call          */
+    double** cores;             /* host [d] caller-owned device buffers     */
+    const int64_t* capacity;    /* host [d], elements per buffer            */
+    int32_t orth;               /* written: 1 left-orth (all but last core),
+                                   2 right-orth (all but first core)        */
+} tt_out;
+
+typedef struct {
+    tt_prec prec;       /* partial-contraction precision, default F64        */
+    double f_init;      /* initial sketch fraction, <= 0 means 0.1 (Sec. 3.3) */
+    double nrmx;        /* ||X|| if known; <= 0: Remark 1 estimate             */
+    int32_t recompress; /* adaptive: 1 = Remark 2 right-to-left truncation
+                           pass with the same threshold tau; 0 = none        */
+    void* stream;       /* hipStream_t; NULL = null stream                    */
+} tt_opts;
+
+typedef struct {        /* diagnostics of the calling thread's last rounding */
+    double tau;         /* per-mode threshold tol*nrmx/sqrt(d-1)             */
+    double nrmx;        /* norm used (given or Remark 1 estimate)            */
+    double min_margin;  /* min |est - tau| / tau over adaptive decisions     */
+    int32_t passes;     /* partial-contraction passes (1 + regenerations)    */
+    int32_t iterations; /* adaptive loop iterations (estimates computed)     */
+} tt_info;
+
+/* Output capacity (elements) per core: cap[k-1] = c_{k-1} n_k c_k with
+ * c_0 = c_d = 1 and c_k = min(r_k, n_1*...*n_k), which bounds the ranks of
+ * every rounding of x (fixed or adaptive; target_ranks is accepted for
+ * symmetry and may be NULL).  TT_EINVAL on a malformed view. */
+tt_status tt_out_capacity(const tt_view* x, const int64_t* target_ranks, int64_t* cap);
+
+/* Fixed-rank randomize-then-orthogonalize rounding with KRP sketches
+ * (Sec. 3.2, Algorithm "Fixed Rank TT-Rounding: Randomize-then-Orthogonalize
+ * using KRP").  Sketch size ell >= 1; the sketch rank at bond k is
+ * l_k = min(ell, l_{k-1} n_k, r_k).  If target_ranks (host [d+1], may be
+ * NULL) asks for fewer than l_k at some bond, a right-to-left SVD truncation
+ * pass (Remark 2) cuts the result to min(target, l_k) there (oversampling).
+ * y->orth is 1 without the pass, 2 with it.  Errors: TT_EINVAL (d < 2,
+ * bad ranks, ell < 1, NULL pointers), TT_ENOMEM (capacity), TT_EDEVICE. */
+tt_status tt_round_fixed(const tt_view* x, const int64_t* target_ranks, int64_t ell,
+                         uint64_t seed, const tt_opts* opts, tt_out* y);
+
+/* Adaptive-rank rounding to relative tolerance tol > 0 (Sec. 3.3, Algorithm
+ * "Adaptive Rank TT-Rounding: Randomize-then-Orthogonalize using KRP", with
+ * the residual sketching of Sec. 3.3 and Remark 1).  With tau =
+ * tol*nrmx/sqrt(d-1), each mode starts from ceil(f_init*rbar_k) sketch
+ * columns and grows by blocks of ell_block (<= 0: ceil(0.05*rbar_k)) while
+ * ||S||_F/sqrt(b) > tau, drawing new Gaussian columns and re-running the
+ * partial contractions on cores k+1..d when the sketch runs out.  Guarantee
+ * (with high probability): ||X - Y|| <= tol ||X||.  Errors as above. */
+tt_status tt_round_adaptive(const tt_view* x, double tol, int64_t ell_block, uint64_t seed,
+                            const tt_opts* opts, tt_out* y);
+
+/* Diagnostics of the calling thread's last tt_round_* call. */
+tt_status tt_last_info(tt_info* info);
+
+/* Thread-local message for the last non-OK status (never NULL). */
+const char* tt_last_error(void);
+
+/* ---- Hot-path components, exported for testing and benchmarking ----- */
+
+/* Omega_mode(:, col0:col0+ncols) as a row-major n x ncols float64 device
+ * array `out` (ld = ncols), mode 1-based (see the generator spec above). */
+tt_status tt_gaussian_factor(uint64_t seed, int32_t mode, int64_t n, int64_t col0,
+                             int64_t ncols, double* out, void* stream);
+
+/* Raw Philox4x32-10 on `count` device counters/keys (uint32 ctr[4*count],
+ * key[2*count]) into out[4*count]; for known-answer tests of the device
+ * generator. */
+tt_status tt_philox4x32_10(const uint32_t* ctr, const uint32_t* key, uint32_t* out,
+                           int64_t count, void* stream);
+
+/* Right-to-left KRP partial contractions (Sec. 3.1, Eq. 7-8):
+ * W_d = H(X_d) Omega_d, W_k = H(X_k)[W_{k+1} (.) Omega_k], for k = d..t
+ * over sketch columns [col0, col0+ncols), computed in `prec`.  w[k-t] is a
+ * device float64 buffer for W_k of shape r_{k-1} x ncols, row-major
+ * (ld = ncols), k = t..d; values are returned unscaled in float64. */
+tt_status tt_partial_contractions(const tt_view* x, uint64_t seed, int64_t col0, int64_t ncols,
+                                  int32_t t, tt_prec prec, double* const* w, void* stream);
+
+/* Thin QR with diag(R) >= 0 of an m x b column-major float64 device matrix
+ * a (ld = m), m >= b >= 1, b <= 64: on return a holds Q (explicit).  The
+ * same routine the rounding uses for its sketches. */
+tt_status tt_qr(double* a, int64_t m, int64_t b, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TTROUND_H */

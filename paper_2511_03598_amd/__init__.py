@@ -1,0 +1,229 @@
+"""Python binding of libttround.so: KRP-sketched randomized TT-rounding on
+MI355X (gfx950).
+
+This module only marshals arguments for the C ABI declared in
+include/ttround.h; every step of the rounding runs in the library's HIP
+kernels.  PyTorch provides device memory and streams.  If the shared
+library is missing, every call raises: there is no fallback.
+
+TT tensors are lists of float64 CUDA tensors of shape (r_{k-1}, n_k, r_k),
+r_0 = r_d = 1 (contiguous).
+"""
+import ctypes
+import os
+
+__all__ = ["lib", "round_fixed", "round_adaptive", "gaussian_factor", "philox4x32_10",
+           "partial_contractions", "qr", "out_capacity", "last_info", "TTError",
+           "PREC_F64", "PREC_F32", "PREC_BF16", "LIB_PATH"]
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libttround.so")
+
+PREC_F64, PREC_F32, PREC_BF16 = 0, 1, 2
+_PREC = {"f64": 0, "fp64": 0, "float64": 0, "f32": 1, "fp32": 1, "float32": 1,
+         "bf16": 2, "bfloat16": 2, 0: 0, 1: 1, 2: 2}
+
+_STATUS = {0: "TT_OK", 1: "TT_PENDING", -1: "TT_EINVAL", -2: "TT_ENOMEM", -3: "TT_ECAPACITY",
+           -4: "TT_EDEVICE", -5: "TT_ENOTFOUND", -6: "TT_EUNSUPPORTED"}
+
+
+class TTError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("%s: %s" % (_STATUS.get(status, status), msg))
+        self.status = status
+
+
+class _View(ctypes.Structure):
+    _fields_ = [("d", ctypes.c_int32), ("n", ctypes.POINTER(ctypes.c_int64)),
+                ("ranks", ctypes.POINTER(ctypes.c_int64)),
+                ("cores", ctypes.POINTER(ctypes.c_void_p))]
+
+
+class _Out(ctypes.Structure):
+    _fields_ = [("d", ctypes.c_int32), ("ranks", ctypes.POINTER(ctypes.c_int64)),
+                ("cores", ctypes.POINTER(ctypes.c_void_p)),
+                ("capacity", ctypes.POINTER(ctypes.c_int64)), ("orth", ctypes.c_int32)]
+
+
+class _Opts(ctypes.Structure):
+    _fields_ = [("prec", ctypes.c_int), ("f_init", ctypes.c_double), ("nrmx", ctypes.c_double),
+                ("recompress", ctypes.c_int32), ("stream", ctypes.c_void_p)]
+
+
+class _Info(ctypes.Structure):
+    _fields_ = [("tau", ctypes.c_double), ("nrmx", ctypes.c_double),
+                ("min_margin", ctypes.c_double), ("passes", ctypes.c_int32),
+                ("iterations", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libttround.so (once).  Raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libttround.so is not built (run __graft_entry__.build() or "
+                               "python -m paper_2511_03598_amd.build); there is no fallback")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i64, u64, i32, dbl = ctypes.c_void_p, ctypes.c_int64, ctypes.c_uint64, ctypes.c_int32, ctypes.c_double
+        P = ctypes.POINTER
+        sig = {
+            "tt_out_capacity": [P(_View), P(i64), P(i64)],
+            "tt_round_fixed": [P(_View), P(i64), i64, u64, P(_Opts), P(_Out)],
+            "tt_round_adaptive": [P(_View), dbl, i64, u64, P(_Opts), P(_Out)],
+            "tt_last_info": [P(_Info)],
+            "tt_gaussian_factor": [u64, i32, i64, i64, i64, vp, vp],
+            "tt_philox4x32_10": [vp, vp, vp, i64, vp],
+            "tt_partial_contractions": [P(_View), u64, i64, i64, i32, ctypes.c_int, P(vp), vp],
+            "tt_qr": [vp, i64, i64, vp],
+        }
+        for name, args in sig.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = ctypes.c_int
+        L.tt_last_error.argtypes = []
+        L.tt_last_error.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+def _check(status):
+    if status != 0:
+        raise TTError(status, lib().tt_last_error().decode())
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream(stream):
+    torch = _torch()
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+class _ViewHolder:
+    """Keeps the ctypes arrays of a tt_view alive."""
+
+    def __init__(self, cores):
+        torch = _torch()
+        d = len(cores)
+        if d < 2:
+            raise ValueError("a TT needs d >= 2 cores")
+        for c in cores:
+            if c.dtype != torch.float64 or not c.is_cuda or c.dim() != 3 or not c.is_contiguous():
+                raise ValueError("cores must be contiguous float64 CUDA tensors of rank 3")
+        self.cores = cores
+        self.dims = [int(c.shape[1]) for c in cores]
+        self.ranks = [1] + [int(c.shape[2]) for c in cores]
+        self.n_arr = (ctypes.c_int64 * d)(*self.dims)
+        self.r_arr = (ctypes.c_int64 * (d + 1))(*self.ranks)
+        self.p_arr = (ctypes.c_void_p * d)(*[c.data_ptr() for c in cores])
+        self.view = _View(d, self.n_arr, self.r_arr, self.p_arr)
+
+
+def out_capacity(cores):
+    h = _ViewHolder(cores)
+    d = len(cores)
+    cap = (ctypes.c_int64 * d)()
+    _check(lib().tt_out_capacity(ctypes.byref(h.view), None, cap))
+    return list(cap)
+
+
+def _run(cores, call):
+    torch = _torch()
+    h = _ViewHolder(cores)
+    d = len(cores)
+    caps = out_capacity(cores)
+    bufs = [torch.empty(max(int(c), 1), dtype=torch.float64, device=cores[0].device) for c in caps]
+    ranks = (ctypes.c_int64 * (d + 1))()
+    ptrs = (ctypes.c_void_p * d)(*[b.data_ptr() for b in bufs])
+    capa = (ctypes.c_int64 * d)(*caps)
+    out = _Out(d, ranks, ptrs, capa, 0)
+    _check(call(h, out))
+    rk = list(ranks)
+    res = [bufs[k][: rk[k] * h.dims[k] * rk[k + 1]].view(rk[k], h.dims[k], rk[k + 1])
+           for k in range(d)]
+    return res, {"ranks": rk, "orth": int(out.orth), **last_info()}
+
+
+def _opts(prec, f_init, nrmx, recompress, stream):
+    return _Opts(_PREC[prec], float(f_init or 0.0), float(nrmx or 0.0), int(recompress),
+                 _stream(stream))
+
+
+def round_fixed(cores, ell, seed, target_ranks=None, prec="f64", stream=None):
+    """Fixed-rank Rand-Orth-KRP (sketch size ell), optionally truncated to
+    target_ranks (list of d+1).  Returns (cores, info)."""
+    d = len(cores)
+    tg = None
+    if target_ranks is not None:
+        if len(target_ranks) != d + 1:
+            raise ValueError("target_ranks needs d+1 entries")
+        tg = (ctypes.c_int64 * (d + 1))(*[int(x) for x in target_ranks])
+    o = _opts(prec, 0.0, 0.0, 0, stream)
+    return _run(cores, lambda h, out: lib().tt_round_fixed(
+        ctypes.byref(h.view), tg, int(ell), ctypes.c_uint64(seed), ctypes.byref(o),
+        ctypes.byref(out)))
+
+
+def round_adaptive(cores, tol, ell_block, seed, nrmx=None, f_init=None, recompress=0, prec="f64",
+                   stream=None):
+    """Adaptive-rank Rand-Orth-KRP to relative tolerance tol.  Returns
+    (cores, info)."""
+    o = _opts(prec, f_init, nrmx, recompress, stream)
+    return _run(cores, lambda h, out: lib().tt_round_adaptive(
+        ctypes.byref(h.view), float(tol), int(ell_block), ctypes.c_uint64(seed),
+        ctypes.byref(o), ctypes.byref(out)))
+
+
+def last_info():
+    i = _Info()
+    _check(lib().tt_last_info(ctypes.byref(i)))
+    return {"tau": i.tau, "nrmx": i.nrmx, "min_margin": i.min_margin, "passes": i.passes,
+            "iterations": i.iterations}
+
+
+def gaussian_factor(seed, mode, n, col0, ncols, device="cuda", stream=None):
+    torch = _torch()
+    out = torch.empty((n, ncols), dtype=torch.float64, device=device)
+    _check(lib().tt_gaussian_factor(ctypes.c_uint64(seed), int(mode), int(n), int(col0),
+                                    int(ncols), ctypes.c_void_p(out.data_ptr()), _stream(stream)))
+    return out
+
+
+def philox4x32_10(ctr, key, stream=None):
+    """ctr: int32 CUDA tensor (count, 4), key: int32 CUDA tensor (count, 2),
+    both holding uint32 bit patterns.  Returns int32 (count, 4)."""
+    torch = _torch()
+    count = int(ctr.shape[0])
+    out = torch.empty((count, 4), dtype=torch.int32, device=ctr.device)
+    _check(lib().tt_philox4x32_10(ctypes.c_void_p(ctr.data_ptr()), ctypes.c_void_p(key.data_ptr()),
+                                  ctypes.c_void_p(out.data_ptr()), count, _stream(stream)))
+    return out
+
+
+def partial_contractions(cores, seed, col0, ncols, t=2, prec="f64", stream=None):
+    """W_k for k = t..d (1-based) over sketch columns [col0, col0+ncols);
+    returns a list [W_t, ..., W_d] of float64 (r_{k-1} x ncols) tensors."""
+    torch = _torch()
+    h = _ViewHolder(cores)
+    d = len(cores)
+    ws = [torch.empty((h.ranks[k - 1], ncols), dtype=torch.float64, device=cores[0].device)
+          for k in range(t, d + 1)]
+    arr = (ctypes.c_void_p * len(ws))(*[w.data_ptr() for w in ws])
+    _check(lib().tt_partial_contractions(ctypes.byref(h.view), ctypes.c_uint64(seed), int(col0),
+                                         int(ncols), int(t), _PREC[prec], arr, _stream(stream)))
+    return ws
+
+
+def qr(a, stream=None):
+    """Thin QR (diag(R) >= 0) of an (m x b) float64 CUDA tensor; returns Q."""
+    torch = _torch()
+    m, b = a.shape
+    buf = a.t().contiguous()  # column-major m x b
+    _check(lib().tt_qr(ctypes.c_void_p(buf.data_ptr()), int(m), int(b), _stream(stream)))
+    return buf.t()

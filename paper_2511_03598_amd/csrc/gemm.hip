@@ -1,0 +1,214 @@
+// General float64 GEMM on MFMA (v_mfma_f64_16x16x4_f64) for the
+// randomize-then-orthogonalize sweep (Sec. 3.2-3.3): the sketch
+// S_k = V(Y_k) W_{k+1}, the projections Q^T S and Q^T V(Y_k), the next core
+// M_k H(X_{k+1}) and the recompression products.
+//
+// 64x64 output tile per 256-thread workgroup, K staged through LDS in
+// 16-deep double-buffered slabs, each wave owning a 32x32 quadrant
+// (2x2 MFMA blocks).  Operands are addressed by element strides so one
+// kernel serves every transpose; the global->LDS thread mapping follows the
+// contiguous dimension so loads stay coalesced.  Split-K writes partial
+// tiles that a second kernel sums in a fixed order (deterministic).
+#include "kernels.hpp"
+
+namespace ttr {
+namespace {
+
+constexpr int BM = 64, BN = 64, BK = 16, LDP = BM + 4;
+
+struct Tile {
+    double a[4], b[4];
+};
+
+__device__ __forceinline__ void load_tiles(const GemmArgs& g, int m0, int n0, int k0, int kend,
+                                           Tile& t) {
+    const int tid = threadIdx.x;
+    // A: 64 (m) x 16 (k)
+    if (g.sak == 1) {
+        const int m = tid >> 2, kk = (tid & 3) * 4;
+        const int gm = m0 + m;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int gk = k0 + kk + q;
+            t.a[q] = (gm < g.M && gk < kend) ? g.A[(size_t)gm * g.sam + gk] : 0.0;
+        }
+    } else {
+        const int kk = tid >> 4, m = (tid & 15) * 4;
+        const int gk = k0 + kk;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int gm = m0 + m + q;
+            t.a[q] = (gm < g.M && gk < kend) ? g.A[(size_t)gm * g.sam + (size_t)gk * g.sak] : 0.0;
+        }
+    }
+    // B: 16 (k) x 64 (n)
+    if (g.sbn == 1 || g.sbk != 1) {
+        const int kk = tid >> 4, nn = (tid & 15) * 4;
+        const int gk = k0 + kk;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int gn = n0 + nn + q;
+            double v = 0.0;
+            if (gk < kend && gn < g.N) {
+                const size_t off = (size_t)gk * g.sbk + (size_t)gn * g.sbn;
+                if (g.Bf) {
+                    v = (double)g.Bf[off];
+                    if (g.bexp) v = ldexp(v, g.bexp[gn]);
+                } else {
+                    v = g.B[off];
+                }
+            }
+            t.b[q] = v;
+        }
+    } else {
+        const int nn = tid >> 2, kk = (tid & 3) * 4;
+        const int gn = n0 + nn;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int gk = k0 + kk + q;
+            double v = 0.0;
+            if (gk < kend && gn < g.N) {
+                const size_t off = (size_t)gk + (size_t)gn * g.sbn;
+                if (g.Bf) {
+                    v = (double)g.Bf[off];
+                    if (g.bexp) v = ldexp(v, g.bexp[gn]);
+                } else {
+                    v = g.B[off];
+                }
+            }
+            t.b[q] = v;
+        }
+    }
+}
+
+__device__ __forceinline__ void store_tiles(const GemmArgs& g, const Tile& t, double (*As)[LDP],
+                                            double (*Bs)[LDP]) {
+    const int tid = threadIdx.x;
+    if (g.sak == 1) {
+        const int m = tid >> 2, kk = (tid & 3) * 4;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) As[kk + q][m] = t.a[q];
+    } else {
+        const int kk = tid >> 4, m = (tid & 15) * 4;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) As[kk][m + q] = t.a[q];
+    }
+    if (g.sbn == 1 || g.sbk != 1) {
+        const int kk = tid >> 4, nn = (tid & 15) * 4;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) Bs[kk][nn + q] = t.b[q];
+    } else {
+        const int nn = tid >> 2, kk = (tid & 3) * 4;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) Bs[kk + q][nn] = t.b[q];
+    }
+}
+
+__global__ void __launch_bounds__(256) gemm_kernel(GemmArgs g, int kchunk, double* partials) {
+    __shared__ double As[2][BK][LDP];
+    __shared__ double Bs[2][BK][LDP];
+    const int m0 = blockIdx.x * BM, n0 = blockIdx.y * BN;
+    const int kbeg = blockIdx.z * kchunk;
+    const int kend = min(g.K, kbeg + kchunk);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int li = lane & 15, lg = lane >> 4;
+    const int wm = (w & 1) * 32, wn = (w >> 1) * 32;
+
+    double4_t acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = double4_t{0, 0, 0, 0};
+
+    Tile t;
+    int buf = 0;
+    if (kbeg < kend) {
+        load_tiles(g, m0, n0, kbeg, kend, t);
+        store_tiles(g, t, As[0], Bs[0]);
+    }
+    __syncthreads();
+    for (int k0 = kbeg; k0 < kend; k0 += BK) {
+        const bool more = k0 + BK < kend;
+        if (more) load_tiles(g, m0, n0, k0 + BK, kend, t);
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const int kk = 4 * s + lg;
+            double av[2], bv[2];
+#pragma unroll
+            for (int i = 0; i < 2; ++i) av[i] = As[buf][kk][wm + i * 16 + li];
+#pragma unroll
+            for (int j = 0; j < 2; ++j) bv[j] = Bs[buf][kk][wn + j * 16 + li];
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j) acc[i][j] = mfma_f64_16x16x4(av[i], bv[j], acc[i][j]);
+        }
+        if (more) store_tiles(g, t, As[buf ^ 1], Bs[buf ^ 1]);
+        __syncthreads();
+        buf ^= 1;
+    }
+    const bool split = gridDim.z > 1;
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int row = m0 + wm + i * 16 + 4 * lg + v;
+                const int col = n0 + wn + j * 16 + li;
+                if (row < g.M && col < g.N) {
+                    if (split) {
+                        partials[((size_t)blockIdx.z * g.M + row) * g.N + col] = acc[i][j][v];
+                    } else {
+                        double* c = g.C + (size_t)row * g.scm + (size_t)col * g.scn;
+                        double val = g.alpha * acc[i][j][v];
+                        if (g.beta != 0.0) val += g.beta * (*c);
+                        *c = val;
+                    }
+                }
+            }
+        }
+    }
+}
+
+__global__ void __launch_bounds__(256) gemm_reduce_kernel(GemmArgs g, int splits,
+                                                          const double* partials) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t mn = (int64_t)g.M * g.N;
+    if (t >= mn) return;
+    double s = 0.0;
+    for (int z = 0; z < splits; ++z) s += partials[(size_t)z * mn + t];
+    const int row = (int)(t / g.N), col = (int)(t - (int64_t)row * g.N);
+    double* c = g.C + (size_t)row * g.scm + (size_t)col * g.scn;
+    double val = g.alpha * s;
+    if (g.beta != 0.0) val += g.beta * (*c);
+    *c = val;
+}
+
+}  // namespace
+
+void launch_gemm(const GemmArgs& g, int splits, double* partials, hipStream_t s) {
+    if (g.M <= 0 || g.N <= 0) return;
+    if (g.K <= 0) splits = 1;
+    if (splits < 1) splits = 1;
+    int kchunk = g.K;
+    if (splits > 1) {
+        kchunk = ((ceil_div(g.K, splits) + BK - 1) / BK) * BK;
+        splits = ceil_div(g.K, kchunk);
+    }
+    if (splits <= 1) {
+        splits = 1;
+        kchunk = g.K > 0 ? g.K : 1;
+    }
+    dim3 grid(ceil_div(g.M, BM), ceil_div(g.N, BN), splits);
+    hipLaunchKernelGGL(gemm_kernel, grid, dim3(256), 0, s, g, kchunk, partials);
+    TTR_CHECK_LAUNCH();
+    if (splits > 1) {
+        const int64_t mn = (int64_t)g.M * g.N;
+        hipLaunchKernelGGL(gemm_reduce_kernel, dim3(ceil_div(mn, 256)), dim3(256), 0, s, g, splits,
+                           partials);
+        TTR_CHECK_LAUNCH();
+    }
+}
+
+}  // namespace ttr

@@ -1,0 +1,108 @@
+// Launch interfaces of the device kernels of libttround (gfx950).
+#pragma once
+
+#include "common.hpp"
+
+namespace ttr {
+
+// ---- Gaussian mode factors (omega.hip) ------------------------------------
+struct OmegaArgs {
+    uint64_t seed;
+    int first_mode;      // 1-based first mode of the launch
+    const int64_t* n;    // device [nmodes] sizes of modes first_mode, first_mode+1, ...
+    const int64_t* off;  // device [nmodes] element offsets of those Omega_j in `base`
+    double* base;        // storage: Omega_j(i, col) at base[off[j-first_mode] + i*ld + col]
+    int64_t ld;          // row stride (column capacity)
+    int64_t col0;        // first global sketch column generated
+    int64_t store_col0;  // storage column where global column col0 goes
+    int64_t ncols;
+};
+void launch_omega(const OmegaArgs& a, int nmodes, int64_t max_n, hipStream_t s);
+void launch_philox(const uint32_t* ctr, const uint32_t* key, uint32_t* out, int64_t count,
+                   hipStream_t s);
+
+// ---- KRP partial contraction of one core (partial.hip) --------------------
+// W_k(a, c) = sum_i Omega_k(i, c) sum_b X_k(a, i, b) W_{k+1}(b, c) for
+// storage columns c in [c0, c0+nc).  W storage is row-major with stride ldw.
+// For reduced precision W is float with a per-column int exponent:
+// true W_k(:, c) = stored(:, c) * 2^colexp_k[c].
+struct PcArgs {
+    const double* X;     // core k (r0 x n x r1), float64
+    int r0, n, r1;
+    const void* Wn;      // W_{k+1} storage (nullptr: the last core, W_{d+1} = 1)
+    const double* Om;    // Omega_k storage, row stride ldo
+    int64_t ldo;
+    void* Wout;          // W_k storage
+    int64_t ldw;
+    int c0, nc;
+    // reduced precision only:
+    const int* in_maxexp;   // max exponent over the pass's block of W_{k+1} (nullptr at k=d)
+    int* out_maxexp;        // atomicMax slot for W_k's block
+    const int* in_colexp;   // colexp_{k+1} (nullptr at k=d)
+    int* out_colexp;        // colexp_k
+};
+void launch_pc_f64(const PcArgs& a, hipStream_t s);
+void launch_pc_f32(const PcArgs& a, hipStream_t s);
+void launch_fill_int(int* p, int value, int64_t count, hipStream_t s);
+// Convert reduced-precision W (float + colexp) to float64 (for the ABI).
+void launch_w_to_f64(const float* w, const int* colexp, int64_t ldw, int rows, int c0, int nc,
+                     double* out, int64_t ldo, hipStream_t s);
+
+// ---- general float64 MFMA GEMM (gemm.hip) ----------------------------------
+// C(m,n) = alpha * sum_k A(m,k) B(k,n) + beta * C(m,n), with arbitrary
+// element strides.  B may instead be float storage Bf with a per-column
+// power-of-two exponent bexp[n] (true B = Bf * 2^bexp[n]).
+struct GemmArgs {
+    int M, N, K;
+    const double* A;
+    int64_t sam, sak;
+    const double* B;
+    const float* Bf;
+    const int* bexp;
+    int64_t sbk, sbn;
+    double* C;
+    int64_t scm, scn;
+    double alpha, beta;
+};
+// `partials` must hold splits*M*N doubles when splits > 1.
+void launch_gemm(const GemmArgs& g, int splits, double* partials, hipStream_t s);
+
+// ---- small utilities (util.hip) --------------------------------------------
+// dst(i, j) = src(i, j) for a rows x cols matrix with arbitrary strides.
+void launch_copy2d(const double* src, int64_t ssr, int64_t ssc, double* dst, int64_t dsr,
+                   int64_t dsc, int rows, int cols, double scale, hipStream_t s);
+// Deterministic sum of squares of a rows x cols strided matrix into *out
+// (device).  `partial` holds >= 1024 doubles, `counter` one zeroed int.
+void launch_sumsq(const double* a, int64_t sr, int64_t sc, int rows, int cols, double* out,
+                  double* partial, int* counter, hipStream_t s);
+
+// ---- thin QR, TSQR with Householder leaves (qr.hip) ------------------------
+struct QrPlan {
+    int m, b, lda;
+    int hmax;      // max rows per leaf
+    int P;         // leaves
+    int levels;    // tree levels above the leaves
+    int nodes;     // total nodes (leaves + internal)
+    size_t lds_bytes;
+};
+QrPlan plan_qr(int m, int b, int lda);
+size_t qr_workspace_doubles(const QrPlan& p);
+// a (m x b, column-major, lda) is overwritten by Q with diag(R) >= 0.  If
+// r_out is non-null, R (b x b, column-major, upper) is written there.
+// `ws` holds qr_workspace_doubles(p) doubles, `counters` p.nodes zeroed ints
+// (they are left zeroed on return).
+void launch_qr(const QrPlan& p, double* a, double* r_out, double* ws, int* counters,
+               hipStream_t s);
+
+// ---- small SVD by one-sided Jacobi (svd.hip) -------------------------------
+// A (p x q, column-major, lda), p >= q, q <= 64.  On return: G (p x q,
+// ld p) holds A*V with columns sorted by decreasing norm (= U*Sigma), Vs
+// (q x q, ld q) the matching right singular vectors, sig[q] the singular
+// values, and *t_out the kept rank: the smallest t >= 1 whose tail
+// sqrt(sum_{j>=t} sig_j^2) <= tau if tau >= 0, else min(max(target,1), q).
+void launch_svd_jacobi(const double* A, int lda, int p, int q, double* G, double* Vs,
+                       double* sig, double tau, int target, int* t_out, hipStream_t s);
+
+int device_lds_limit();
+
+}  // namespace ttr

@@ -1,0 +1,625 @@
+// Host runtime of libttround: the launch sequences of the KRP roundings.
+//
+//  fixed rank (Sec. 3.2):   Omega -> partial contractions W_d..W_2 ->
+//     for k = 1..d-1: S = V(Y_k) W_{k+1}; Q = qr(S); M = Q^T V(Y_k);
+//     V(Y_k) <- Q; H(Y_{k+1}) = M H(X_{k+1})  -> optional Remark 2 pass.
+//  adaptive (Sec. 3.3):     same sweep, growing Q by residual sketches
+//     S = V(Y_k) W_{k+1}(:, new); S -= Q Q^T S; est = ||S||_F / sqrt(b);
+//     while est > tau: Q_new = qr(S); Q_new = qr(Q_new - Q Q^T Q_new); ...
+//     The projection M and the next core are formed once at loop exit
+//     (the same product as the paper's row-by-row appends).
+//
+// Every step runs in the library's HIP kernels; the host only sequences
+// launches and, in the adaptive loop, reads back the scalar estimate.
+#include "runtime.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <climits>
+#include <memory>
+#include <mutex>
+
+namespace ttr {
+
+// ---------------------------------------------------------------------------
+// Device buffers and the workspace pool
+// ---------------------------------------------------------------------------
+namespace {
+
+struct DevBuf {
+    void* p = nullptr;
+    size_t cap = 0;
+    void* get(size_t bytes) {
+        if (bytes == 0) bytes = 256;
+        if (bytes > cap) {
+            if (p) TTR_HIP(hipFree(p));
+            p = nullptr;
+            cap = 0;
+            const size_t want = bytes + bytes / 4;
+            if (hipMalloc(&p, want) != hipSuccess) {
+                (void)hipGetLastError();
+                p = nullptr;
+                throw Error(-2, "device allocation of " + std::to_string(want) + " bytes failed");
+            }
+            cap = want;
+        }
+        return p;
+    }
+    template <typename T>
+    T* as(size_t count) {
+        return static_cast<T*>(get(count * sizeof(T)));
+    }
+    ~DevBuf() {
+        if (p) (void)hipFree(p);
+    }
+};
+
+struct Workspace {
+    int device = -1;
+    DevBuf omega, w, colexp, maxexp, dn, doff, y0, y1, q, sbuf, tbuf, m, qrws, qrcnt, part, scal,
+        sumpart, sumcnt, small1, small2, small3, small4, tint, tmp;
+    double* host = nullptr;  // pinned scalars
+    int* host_int = nullptr;
+    int zeroed_qrcnt = 0, zeroed_sumcnt = 0;
+    Workspace() {
+        TTR_HIP(hipGetDevice(&device));
+        TTR_HIP(hipHostMalloc((void**)&host, 64 * sizeof(double), hipHostMallocDefault));
+        host_int = reinterpret_cast<int*>(host + 32);
+    }
+    ~Workspace() {
+        if (host) (void)hipHostFree(host);
+    }
+    int* qr_counters(int n, hipStream_t s) {
+        const size_t before = qrcnt.cap;
+        int* p = qrcnt.as<int>(std::max(n, 1024));
+        if (qrcnt.cap != before || !zeroed_qrcnt) {
+            launch_fill_int(p, 0, (int64_t)(qrcnt.cap / sizeof(int)), s);
+            zeroed_qrcnt = 1;
+        }
+        return p;
+    }
+    int* sum_counter(hipStream_t s) {
+        const size_t before = sumcnt.cap;
+        int* p = sumcnt.as<int>(16);
+        if (sumcnt.cap != before || !zeroed_sumcnt) {
+            launch_fill_int(p, 0, (int64_t)(sumcnt.cap / sizeof(int)), s);
+            zeroed_sumcnt = 1;
+        }
+        return p;
+    }
+};
+
+std::mutex g_pool_mu;
+std::vector<std::unique_ptr<Workspace>> g_pool;
+
+struct WsLease {
+    std::unique_ptr<Workspace> ws;
+    WsLease() {
+        int dev = 0;
+        TTR_HIP(hipGetDevice(&dev));
+        {
+            std::lock_guard<std::mutex> lk(g_pool_mu);
+            for (size_t i = 0; i < g_pool.size(); ++i) {
+                if (g_pool[i]->device == dev) {
+                    ws = std::move(g_pool[i]);
+                    g_pool.erase(g_pool.begin() + i);
+                    break;
+                }
+            }
+        }
+        if (!ws) ws.reset(new Workspace());
+    }
+    ~WsLease() {
+        if (ws) {
+            std::lock_guard<std::mutex> lk(g_pool_mu);
+            g_pool.push_back(std::move(ws));
+        }
+    }
+    Workspace* operator->() { return ws.get(); }
+};
+
+// ---------------------------------------------------------------------------
+// Thin wrappers
+// ---------------------------------------------------------------------------
+void gemm(Workspace& ws, hipStream_t s, int M, int N, int K, const double* A, int64_t sam,
+          int64_t sak, const double* B, int64_t sbk, int64_t sbn, double* C, int64_t scm,
+          int64_t scn, double alpha = 1.0, double beta = 0.0, const float* Bf = nullptr,
+          const int* bexp = nullptr) {
+    if (M <= 0 || N <= 0) return;
+    GemmArgs g{};
+    g.M = M;
+    g.N = N;
+    g.K = K;
+    g.A = A;
+    g.sam = sam;
+    g.sak = sak;
+    g.B = B;
+    g.Bf = Bf;
+    g.bexp = bexp;
+    g.sbk = sbk;
+    g.sbn = sbn;
+    g.C = C;
+    g.scm = scm;
+    g.scn = scn;
+    g.alpha = alpha;
+    g.beta = beta;
+    const int tiles = ceil_div(M, 64) * ceil_div(N, 64);
+    int splits = 1;
+    if (tiles < 128 && K >= 512) {
+        splits = std::min(ceil_div(K, 256), std::max(1, 256 / tiles));
+        splits = std::min(splits, 64);
+    }
+    double* partials = nullptr;
+    if (splits > 1) partials = ws.part.as<double>((size_t)splits * M * N);
+    launch_gemm(g, splits, partials, s);
+}
+
+void qr(Workspace& ws, hipStream_t s, double* a, int m, int b, int lda, double* r_out = nullptr) {
+    const QrPlan p = plan_qr(m, b, lda);
+    double* w = ws.qrws.as<double>(qr_workspace_doubles(p));
+    int* cnt = ws.qr_counters(p.nodes, s);
+    launch_qr(p, a, r_out, w, cnt, s);
+}
+
+double read_scalar(Workspace& ws, hipStream_t s, const double* dev) {
+    TTR_HIP(hipMemcpyAsync(ws.host, dev, sizeof(double), hipMemcpyDeviceToHost, s));
+    TTR_HIP(hipStreamSynchronize(s));
+    return ws.host[0];
+}
+
+int read_int(Workspace& ws, hipStream_t s, const int* dev) {
+    TTR_HIP(hipMemcpyAsync(ws.host_int, dev, sizeof(int), hipMemcpyDeviceToHost, s));
+    TTR_HIP(hipStreamSynchronize(s));
+    return ws.host_int[0];
+}
+
+double sumsq(Workspace& ws, hipStream_t s, const double* a, int64_t sr, int64_t sc, int rows,
+             int cols) {
+    double* out = ws.scal.as<double>(8);
+    double* part = ws.sumpart.as<double>(1024);
+    launch_sumsq(a, sr, sc, rows, cols, out, part, ws.sum_counter(s), s);
+    return read_scalar(ws, s, out);
+}
+
+int64_t prod_capped(const std::vector<int64_t>& n, int upto, int64_t cap) {
+    int64_t p = 1;
+    for (int i = 0; i < upto; ++i) {
+        if (p > cap / std::max<int64_t>(n[i], 1)) return cap;
+        p *= n[i];
+    }
+    return std::min(p, cap);
+}
+
+// ---------------------------------------------------------------------------
+// Partial contractions state (Omega and W for modes 2..d)
+// ---------------------------------------------------------------------------
+struct Sketch {
+    const Shape& s;
+    const double* const* cores;
+    uint64_t seed;
+    int prec;
+    int64_t lcap;  // column capacity (storage stride)
+    hipStream_t st;
+    Workspace& ws;
+    std::vector<int64_t> om_off, w_off;  // by 1-based mode
+    double* om = nullptr;
+    void* w = nullptr;
+    int* colexp = nullptr;
+    int* maxexp = nullptr;
+    int64_t* dn = nullptr;
+    int64_t* doff = nullptr;
+    int64_t ncols = 0;  // generated columns (storage col == global col - gcol0)
+    int64_t gcol0 = 0;
+    int passes = 0;
+
+    Sketch(const Shape& sh, const double* const* c, uint64_t sd, int pr, int64_t cap,
+           hipStream_t stream, Workspace& w_, int64_t global_col0 = 0)
+        : s(sh), cores(c), seed(sd), prec(pr), lcap(cap), st(stream), ws(w_), gcol0(global_col0) {
+        const int d = s.d;
+        om_off.assign(d + 2, 0);
+        w_off.assign(d + 2, 0);
+        int64_t o = 0, wo = 0;
+        for (int j = 2; j <= d; ++j) {
+            om_off[j] = o;
+            o += s.n[j - 1] * lcap;
+            w_off[j] = wo;
+            wo += s.r[j - 1] * lcap;
+        }
+        om = ws.omega.as<double>(o);
+        const size_t esz = (prec == 0) ? sizeof(double) : sizeof(float);
+        w = ws.w.get(wo * esz);
+        if (prec != 0) {
+            colexp = ws.colexp.as<int>((size_t)(d + 2) * lcap);
+            maxexp = ws.maxexp.as<int>(d + 2);
+        }
+        // Per-mode sizes/offsets for modes 2..d (uploaded once per call).
+        std::vector<int64_t> hn(d + 1, 0), ho(d + 1, 0);
+        for (int j = 2; j <= d; ++j) {
+            hn[j - 2] = s.n[j - 1];
+            ho[j - 2] = om_off[j];
+        }
+        dn = ws.dn.as<int64_t>(d + 1);
+        doff = ws.doff.as<int64_t>(d + 1);
+        TTR_HIP(hipMemcpyAsync(dn, hn.data(), (d + 1) * sizeof(int64_t), hipMemcpyHostToDevice, st));
+        TTR_HIP(hipMemcpyAsync(doff, ho.data(), (d + 1) * sizeof(int64_t), hipMemcpyHostToDevice, st));
+    }
+
+    double* omega(int j) { return om + om_off[j]; }
+    double* wd(int k) { return static_cast<double*>(w) + w_off[k]; }
+    float* wf(int k) { return static_cast<float*>(w) + w_off[k]; }
+    const int* cexp(int k) const { return colexp ? colexp + (size_t)k * lcap : nullptr; }
+
+    // Generate columns [ncols, ncols+nc) of Omega_t..Omega_d and contract
+    // cores t..d (one right-to-left pass).
+    void pass(int t, int64_t nc) {
+        const int d = s.d;
+        if (nc <= 0) return;
+        if (ncols + nc > lcap) throw Error(-6, "sketch column capacity exceeded");
+        OmegaArgs oa{};
+        oa.seed = seed;
+        oa.first_mode = t;
+        oa.n = dn + (t - 2);
+        oa.off = doff + (t - 2);
+        oa.base = om;
+        oa.ld = lcap;
+        oa.col0 = gcol0 + ncols;
+        oa.store_col0 = ncols;
+        oa.ncols = nc;
+        int64_t maxn = 1;
+        for (int j = t; j <= d; ++j) maxn = std::max(maxn, s.n[j - 1]);
+        launch_omega(oa, d - t + 1, maxn, st);
+        if (prec != 0) launch_fill_int(maxexp, INT_MIN, d + 2, st);
+        for (int k = d; k >= t; --k) {
+            PcArgs a{};
+            a.X = cores[k - 1];
+            a.r0 = (int)s.r[k - 1];
+            a.n = (int)s.n[k - 1];
+            a.r1 = (int)s.r[k];
+            a.Om = omega(k);
+            a.ldo = lcap;
+            a.ldw = lcap;
+            a.c0 = (int)ncols;
+            a.nc = (int)nc;
+            if (prec == 0) {
+                a.Wn = (k == d) ? nullptr : (const void*)wd(k + 1);
+                a.Wout = wd(k);
+                launch_pc_f64(a, st);
+            } else {
+                a.Wn = (k == d) ? nullptr : (const void*)wf(k + 1);
+                a.Wout = wf(k);
+                a.in_maxexp = (k == d) ? nullptr : maxexp + (k + 1);
+                a.out_maxexp = maxexp + k;
+                a.in_colexp = (k == d) ? nullptr : colexp + (size_t)(k + 1) * lcap;
+                a.out_colexp = colexp + (size_t)k * lcap;
+                launch_pc_f32(a, st);
+            }
+        }
+        ncols += nc;
+        ++passes;
+    }
+
+    // S(rows x nb) = Z(rows x K) * W_{k+1}(:, c0:c0+nb), S column-major (ld).
+    void sketch_gemm(int k, const double* Z, int rows, int K, int64_t c0, int nb, double* S,
+                     int64_t ld) {
+        if (prec == 0)
+            gemm(ws, st, rows, nb, K, Z, K, 1, wd(k + 1) + c0, lcap, 1, S, 1, ld);
+        else
+            gemm(ws, st, rows, nb, K, Z, K, 1, nullptr, lcap, 1, S, 1, ld, 1.0, 0.0,
+                 wf(k + 1) + c0, cexp(k + 1) + c0);
+    }
+};
+
+// Right-to-left truncation pass (Remark 2) on caller cores in place.  tau >=
+// 0 selects the tail rule, else target ranks (host [d+1]).
+void recompress(Workspace& ws, hipStream_t st, const Shape& s, double** cores, int64_t* ranks,
+                double tau, const int64_t* target) {
+    const int d = s.d;
+    int64_t maxcore = 0, maxrows = 0;
+    for (int k = 1; k <= d; ++k) {
+        maxcore = std::max(maxcore, ranks[k - 1] * s.n[k - 1] * ranks[k]);
+        maxrows = std::max(maxrows, ranks[k - 1] * s.n[k - 1]);
+    }
+    double* tmp = ws.tmp.as<double>(maxcore + 64);
+    for (int k = d; k >= 2; --k) {
+        const int b = (int)ranks[k - 1];
+        const int m = (int)(s.n[k - 1] * ranks[k]);
+        double* H = cores[k - 1];  // b x m row-major
+        if (b > 64) throw Error(-6, "recompression supports ranks <= 64");
+        double* A = ws.small1.as<double>((size_t)b * b + 64);
+        double* G = ws.small2.as<double>((size_t)b * b + 64);
+        double* Vs = ws.small3.as<double>((size_t)b * b + 64);
+        double* sig = ws.small4.as<double>(b + 64);
+        int* tdev = ws.tint.as<int>(16);
+        int q;
+        if (m >= b) {
+            // H^T (m x b, column-major) is the row-major H buffer itself.
+            double* R = ws.tbuf.as<double>((size_t)b * b + 64);
+            qr(ws, st, H, m, b, m, R);
+            launch_copy2d(R, b, 1, A, 1, b, b, b, 1.0, st);  // A = R^T, ld b
+            q = b;
+        } else {
+            launch_copy2d(H, m, 1, A, 1, b, b, m, 1.0, st);  // A = H (b x m), ld b
+            q = m;
+        }
+        const int tgt = target ? (int)target[k - 1] : 0;
+        launch_svd_jacobi(A, b, b, q, G, Vs, sig, tau, tgt, tdev, st);
+        const int t = read_int(ws, st, tdev);
+        // New H(Y_k) = V_t^T Q^T (t x m) or V_t^T when m < b.
+        if (m >= b) {
+            gemm(ws, st, t, m, b, Vs, q, 1, H, m, 1, tmp, m, 1);
+        } else {
+            launch_copy2d(Vs, q, 1, tmp, m, 1, t, m, 1.0, st);
+        }
+        TTR_HIP(hipMemcpyAsync(H, tmp, (size_t)t * m * sizeof(double), hipMemcpyDeviceToDevice, st));
+        // V(Y_{k-1}) <- V(Y_{k-1}) G_t.
+        const int rows = (int)(ranks[k - 2] * s.n[k - 2]);
+        gemm(ws, st, rows, t, b, cores[k - 2], b, 1, G, 1, b, tmp, t, 1);
+        TTR_HIP(hipMemcpyAsync(cores[k - 2], tmp, (size_t)rows * t * sizeof(double),
+                               hipMemcpyDeviceToDevice, st));
+        ranks[k - 1] = t;
+    }
+}
+
+void check_capacity(const Shape& s, const std::vector<int64_t>& l, const OutCores& y) {
+    for (int k = 1; k <= s.d; ++k) {
+        const int64_t need = l[k - 1] * s.n[k - 1] * l[k];
+        if (need > y.cap[k - 1])
+            throw Error(-2, "output core " + std::to_string(k) + " needs " + std::to_string(need) +
+                                " elements, capacity " + std::to_string(y.cap[k - 1]));
+    }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Shapes
+// ---------------------------------------------------------------------------
+Shape make_shape(int d, const int64_t* n, const int64_t* ranks) {
+    if (d < 2) throw Error(-1, "d must be >= 2");
+    if (!n || !ranks) throw Error(-1, "null dims or ranks");
+    Shape s;
+    s.d = d;
+    s.n.assign(n, n + d);
+    s.r.assign(ranks, ranks + d + 1);
+    if (s.r[0] != 1 || s.r[d] != 1) throw Error(-1, "ranks[0] and ranks[d] must be 1");
+    for (int k = 0; k < d; ++k) {
+        if (s.n[k] < 1 || s.n[k] > (1 << 20)) throw Error(-1, "mode size out of range");
+        if (s.r[k + 1] < 1 || s.r[k + 1] > (1 << 16)) throw Error(-1, "rank out of range");
+    }
+    for (int k = 0; k < d; ++k)
+        if (s.r[k] * s.n[k] * s.r[k + 1] > ((int64_t)1 << 31))
+            throw Error(-6, "core too large (more than 2^31 elements)");
+    return s;
+}
+
+std::vector<int64_t> rank_caps(const Shape& s) {
+    std::vector<int64_t> c(s.d + 1, 1);
+    for (int k = 1; k < s.d; ++k) c[k] = std::min(s.r[k], prod_capped(s.n, k, INT64_MAX / 4));
+    return c;
+}
+
+// ---------------------------------------------------------------------------
+// Fixed rank (Sec. 3.2)
+// ---------------------------------------------------------------------------
+void round_fixed(const Shape& s, const double* const* cores, const int64_t* target, int64_t ell,
+                 uint64_t seed, const Options& o, OutCores& y, RoundInfo& info) {
+    const int d = s.d;
+    if (ell < 1) throw Error(-1, "ell must be >= 1");
+    if (ell > 64) throw Error(-6, "fixed-rank sketch size ell > 64 is not supported");
+    hipStream_t st = o.stream;
+    WsLease lease;
+    Workspace& ws = *lease.ws;
+
+    std::vector<int64_t> l(d + 1, 1);
+    for (int k = 1; k < d; ++k) l[k] = std::min<int64_t>({ell, l[k - 1] * s.n[k - 1], s.r[k]});
+    check_capacity(s, l, y);
+
+    Sketch sk(s, cores, seed, o.prec, ell, st, ws);
+    sk.pass(2, ell);
+
+    int64_t maxy = 0, maxrows = 0;
+    for (int k = 1; k <= d; ++k) {
+        maxy = std::max(maxy, l[k - 1] * s.n[k - 1] * s.r[k]);
+        maxrows = std::max(maxrows, l[k - 1] * s.n[k - 1]);
+    }
+    double* ybuf[2] = {ws.y0.as<double>(maxy), ws.y1.as<double>(maxy)};
+    double* Q = ws.q.as<double>(maxrows * ell);
+    double* M = ws.m.as<double>((size_t)ell * *std::max_element(s.r.begin(), s.r.end()));
+
+    const double* ycur = cores[0];
+    for (int k = 1; k < d; ++k) {
+        const int rows = (int)(l[k - 1] * s.n[k - 1]);
+        const int cols = (int)s.r[k];
+        const int lk = (int)l[k];
+        sk.sketch_gemm(k, ycur, rows, cols, 0, lk, Q, rows);
+        qr(ws, st, Q, rows, lk, rows);
+        gemm(ws, st, lk, cols, rows, Q, rows, 1, ycur, cols, 1, M, cols, 1);
+        launch_copy2d(Q, 1, rows, y.cores[k - 1], lk, 1, rows, lk, 1.0, st);
+        const int nn = (int)(s.n[k] * s.r[k + 1]);
+        double* dst = (k == d - 1) ? y.cores[d - 1] : ybuf[k & 1];
+        gemm(ws, st, lk, nn, cols, M, cols, 1, cores[k], nn, 1, dst, nn, 1);
+        ycur = dst;
+    }
+    for (int k = 0; k <= d; ++k) y.ranks[k] = l[k];
+    y.orth = 1;
+    bool cut = false;
+    if (target)
+        for (int k = 1; k < d; ++k) cut = cut || (target[k] < l[k]);
+    if (cut) {
+        std::vector<int64_t> tg(d + 1, 1);
+        for (int k = 1; k < d; ++k) tg[k] = std::max<int64_t>(1, std::min(target[k], l[k]));
+        recompress(ws, st, s, y.cores, y.ranks, -1.0, tg.data());
+        y.orth = 2;
+    }
+    TTR_HIP(hipStreamSynchronize(st));
+    info = RoundInfo{};
+    info.passes = sk.passes;
+}
+
+// ---------------------------------------------------------------------------
+// Adaptive rank (Sec. 3.3)
+// ---------------------------------------------------------------------------
+void round_adaptive(const Shape& s, const double* const* cores, double tol, int64_t ell_block,
+                    uint64_t seed, const Options& o, OutCores& y, RoundInfo& info) {
+    const int d = s.d;
+    if (!(tol > 0.0)) throw Error(-1, "tol must be > 0");
+    hipStream_t st = o.stream;
+    WsLease lease;
+    Workspace& ws = *lease.ws;
+    const double f_init = (o.f_init > 0.0) ? o.f_init : 0.1;
+
+    const std::vector<int64_t> cap = rank_caps(s);
+    int64_t rmax = 1, lcap = 1, maxrows = 1, maxy = 1;
+    for (int k = 1; k < d; ++k) {
+        rmax = std::max(rmax, s.r[k]);
+        lcap = std::max(lcap, cap[k]);
+    }
+    for (int k = 1; k <= d; ++k) {
+        maxrows = std::max(maxrows, cap[k - 1] * s.n[k - 1]);
+        maxy = std::max(maxy, cap[k - 1] * s.n[k - 1] * s.r[k]);
+    }
+    const int64_t r0 = (int64_t)std::ceil(f_init * (double)rmax);
+    lcap = std::max(lcap, r0);
+    // Output capacity check against the worst-case ranks.
+    check_capacity(s, cap, y);
+
+    Sketch sk(s, cores, seed, o.prec, lcap, st, ws);
+    sk.pass(2, r0);
+
+    int64_t bmax = 1;
+    for (int k = 1; k < d; ++k) {
+        const int64_t rb = cap[k];
+        const int64_t bi = (int64_t)std::ceil(f_init * (double)rb);
+        const int64_t bl = ell_block > 0 ? ell_block : (int64_t)std::ceil(0.05 * (double)rb);
+        bmax = std::max({bmax, bi, bl});
+    }
+    bmax = std::min(bmax, lcap);
+    if (bmax > 64) throw Error(-6, "adaptive sketch blocks wider than 64 are not supported");
+
+    double* ybuf[2] = {ws.y0.as<double>(maxy), ws.y1.as<double>(maxy)};
+    double* Q = ws.q.as<double>(maxrows * lcap);
+    double* T = ws.tbuf.as<double>(lcap * bmax + 64);
+    double* M = ws.m.as<double>(lcap * rmax);
+
+    double nrmx = o.nrmx;
+    if (!(nrmx > 0.0)) {
+        // Remark 1: ||X|| ~ ||V(X_1) W_2||_F / sqrt(r0).
+        const int rows = (int)s.n[0];
+        double* tmp = ws.sbuf.as<double>((size_t)rows * r0 + 64);
+        sk.sketch_gemm(1, cores[0], rows, (int)s.r[1], 0, (int)r0, tmp, rows);
+        nrmx = std::sqrt(sumsq(ws, st, tmp, 1, rows, rows, (int)r0) / (double)r0);
+    }
+    const double tau = tol * nrmx / std::sqrt((double)(d - 1));
+    info = RoundInfo{};
+    info.tau = tau;
+    info.nrmx = nrmx;
+    info.min_margin = INFINITY;
+
+    const double* ycur = cores[0];
+    int64_t lprev = 1;
+    for (int k = 1; k < d; ++k) {
+        const int rows = (int)(lprev * s.n[k - 1]);
+        const int cols = (int)s.r[k];
+        const int rbar = std::min(rows, cols);
+        const int binit = std::max(1, std::min(rbar, (int)std::ceil(f_init * (double)rbar)));
+        sk.sketch_gemm(k, ycur, rows, cols, 0, binit, Q, rows);
+        qr(ws, st, Q, rows, binit, rows);
+        int ncq = binit;
+        const int blk = ell_block > 0 ? (int)ell_block : (int)std::ceil(0.05 * (double)rbar);
+        while (ncq < rbar) {
+            const int bb = std::min(blk, rbar - ncq);
+            const int64_t need = ncq + bb;
+            if (sk.ncols < need) {
+                const int64_t grow = std::min(lcap - sk.ncols, std::max(need - sk.ncols, sk.ncols));
+                sk.pass(k + 1, grow);
+            }
+            double* S = Q + (size_t)ncq * rows;  // candidate columns follow Q
+            sk.sketch_gemm(k, ycur, rows, cols, ncq, bb, S, rows);
+            // S -= Q (Q^T S)
+            gemm(ws, st, ncq, bb, rows, Q, rows, 1, S, 1, rows, T, bb, 1);
+            gemm(ws, st, rows, bb, ncq, Q, 1, rows, T, bb, 1, S, 1, rows, -1.0, 1.0);
+            const double est = std::sqrt(sumsq(ws, st, S, 1, rows, rows, bb) / (double)bb);
+            info.iterations++;
+            if (tau > 0) info.min_margin = std::min(info.min_margin, std::fabs(est - tau) / tau);
+            if (!(est > tau)) break;
+            qr(ws, st, S, rows, bb, rows);
+            gemm(ws, st, ncq, bb, rows, Q, rows, 1, S, 1, rows, T, bb, 1);
+            gemm(ws, st, rows, bb, ncq, Q, 1, rows, T, bb, 1, S, 1, rows, -1.0, 1.0);
+            qr(ws, st, S, rows, bb, rows);
+            ncq += bb;
+        }
+        const int lk = ncq;
+        gemm(ws, st, lk, cols, rows, Q, rows, 1, ycur, cols, 1, M, cols, 1);
+        launch_copy2d(Q, 1, rows, y.cores[k - 1], lk, 1, rows, lk, 1.0, st);
+        const int nn = (int)(s.n[k] * s.r[k + 1]);
+        double* dst = (k == d - 1) ? y.cores[d - 1] : ybuf[k & 1];
+        gemm(ws, st, lk, nn, cols, M, cols, 1, cores[k], nn, 1, dst, nn, 1);
+        ycur = dst;
+        y.ranks[k] = lk;
+        lprev = lk;
+    }
+    y.ranks[0] = y.ranks[d] = 1;
+    y.orth = 1;
+    if (o.recompress) {
+        recompress(ws, st, s, y.cores, y.ranks, tau, nullptr);
+        y.orth = 2;
+    }
+    TTR_HIP(hipStreamSynchronize(st));
+    info.passes = sk.passes;
+    if (info.iterations == 0) info.min_margin = INFINITY;
+}
+
+// ---------------------------------------------------------------------------
+// Components
+// ---------------------------------------------------------------------------
+void gaussian_factor(uint64_t seed, int mode, int64_t n, int64_t col0, int64_t ncols, double* out,
+                     hipStream_t st) {
+    if (mode < 1 || n < 1 || ncols < 0 || col0 < 0 || !out) throw Error(-1, "bad Omega request");
+    WsLease lease;
+    int64_t* dn = lease->dn.as<int64_t>(2);
+    int64_t* doff = lease->doff.as<int64_t>(2);
+    const int64_t hn[2] = {n, 0}, ho[2] = {0, 0};
+    TTR_HIP(hipMemcpyAsync(dn, hn, sizeof(hn), hipMemcpyHostToDevice, st));
+    TTR_HIP(hipMemcpyAsync(doff, ho, sizeof(ho), hipMemcpyHostToDevice, st));
+    OmegaArgs a{};
+    a.seed = seed;
+    a.first_mode = mode;
+    a.n = dn;
+    a.off = doff;
+    a.base = out;
+    a.ld = ncols;
+    a.col0 = col0;
+    a.store_col0 = 0;
+    a.ncols = ncols;
+    launch_omega(a, 1, n, st);
+    TTR_HIP(hipStreamSynchronize(st));
+}
+
+void partial_contractions(const Shape& s, const double* const* cores, uint64_t seed, int64_t col0,
+                          int64_t ncols, int t, int prec, double* const* w, hipStream_t st) {
+    if (t < 2 || t > s.d) throw Error(-1, "t must be in [2, d]");
+    if (ncols < 1 || col0 < 0) throw Error(-1, "bad column range");
+    if (prec < 0 || prec > 1) throw Error(-6, "precision not supported for partial contractions");
+    WsLease lease;
+    Workspace& ws = *lease.ws;
+    Sketch sk(s, cores, seed, prec, ncols, st, ws, col0);
+    sk.pass(t, ncols);
+    for (int k = t; k <= s.d; ++k) {
+        const int rows = (int)s.r[k - 1];
+        if (prec == 0)
+            launch_copy2d(sk.wd(k), ncols, 1, w[k - t], ncols, 1, rows, (int)ncols, 1.0, st);
+        else
+            launch_w_to_f64(sk.wf(k), sk.cexp(k), ncols, rows, 0, (int)ncols, w[k - t], ncols, st);
+    }
+    TTR_HIP(hipStreamSynchronize(st));
+}
+
+void qr_inplace(double* a, int64_t m, int64_t b, hipStream_t st) {
+    if (!a || m < 1 || b < 1) throw Error(-1, "bad QR request");
+    if (m < b) throw Error(-1, "QR needs m >= b");
+    WsLease lease;
+    qr(*lease.ws, st, a, (int)m, (int)b, (int)m);
+    TTR_HIP(hipStreamSynchronize(st));
+}
+
+}  // namespace ttr

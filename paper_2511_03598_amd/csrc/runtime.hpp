@@ -1,0 +1,53 @@
+// Host runtime of libttround: shape validation, workspace pool, and the
+// launch sequences of the fixed-rank and adaptive KRP roundings.
+#pragma once
+
+#include <vector>
+
+#include "kernels.hpp"
+
+namespace ttr {
+
+struct Shape {
+    int d = 0;
+    std::vector<int64_t> n;  // [d]
+    std::vector<int64_t> r;  // [d+1]
+};
+
+struct Options {
+    int prec = 0;          // 0 f64, 1 f32, 2 bf16 (partial contractions only)
+    double f_init = 0.1;
+    double nrmx = 0.0;     // <= 0: Remark 1 estimate
+    int recompress = 0;
+    hipStream_t stream = nullptr;
+};
+
+struct RoundInfo {
+    double tau = 0, nrmx = 0, min_margin = 0;
+    int passes = 0, iterations = 0;
+};
+
+// Output cores: caller-owned device buffers with capacities (elements).
+struct OutCores {
+    double** cores;
+    const int64_t* cap;
+    int64_t* ranks;  // [d+1], written
+    int orth = 0;    // written: 1 left, 2 right
+};
+
+Shape make_shape(int d, const int64_t* n, const int64_t* ranks);
+// c_k = min(r_k, n_1 ... n_k) (k = 0..d, c_0 = c_d = 1).
+std::vector<int64_t> rank_caps(const Shape& s);
+
+void round_fixed(const Shape& s, const double* const* cores, const int64_t* target, int64_t ell,
+                 uint64_t seed, const Options& o, OutCores& y, RoundInfo& info);
+void round_adaptive(const Shape& s, const double* const* cores, double tol, int64_t ell_block,
+                    uint64_t seed, const Options& o, OutCores& y, RoundInfo& info);
+
+void gaussian_factor(uint64_t seed, int mode, int64_t n, int64_t col0, int64_t ncols, double* out,
+                     hipStream_t st);
+void partial_contractions(const Shape& s, const double* const* cores, uint64_t seed, int64_t col0,
+                          int64_t ncols, int t, int prec, double* const* w, hipStream_t st);
+void qr_inplace(double* a, int64_t m, int64_t b, hipStream_t st);
+
+}  // namespace ttr

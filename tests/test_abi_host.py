@@ -1,0 +1,90 @@
+"""The C ABI library loads, exports every symbol include/ttround.h declares,
+and rejects malformed arguments on the host (no GPU needed: validation
+happens before any device call)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ttround.h")
+
+
+def declared_symbols():
+    text = open(HEADER).read()
+    return re.findall(r"^\s*(?:tt_status|const char\*|void)\s+(tt_\w+)\s*\(", text, re.M)
+
+
+def test_header_declares_the_boundary():
+    names = set(declared_symbols())
+    for n in ("tt_round_fixed", "tt_round_adaptive", "tt_out_capacity", "tt_last_error",
+              "tt_partial_contractions", "tt_gaussian_factor", "tt_qr", "tt_philox4x32_10"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    import paper_2511_03598_amd as ttr
+    L = ttr.lib()
+    missing = [n for n in declared_symbols() if not hasattr(L, n)]
+    assert missing == []
+
+
+def _view(d, n, ranks, ptrs):
+    import paper_2511_03598_amd as ttr
+    na = (ctypes.c_int64 * max(d, 1))(*n)
+    ra = (ctypes.c_int64 * (max(d, 1) + 1))(*ranks)
+    pa = (ctypes.c_void_p * max(d, 1))(*ptrs)
+    return ttr._View(d, na, ra, pa), (na, ra, pa)
+
+
+def test_out_capacity_host_only():
+    import paper_2511_03598_amd as ttr
+    L = ttr.lib()
+    v, keep = _view(3, [4, 5, 6], [1, 7, 9, 1], [1, 2, 3])
+    cap = (ctypes.c_int64 * 3)()
+    assert L.tt_out_capacity(ctypes.byref(v), None, cap) == 0
+    # c = (1, min(7,4), min(9,20), 1) = (1, 4, 9, 1)
+    assert list(cap) == [1 * 4 * 4, 4 * 5 * 9, 9 * 6 * 1]
+
+
+@pytest.mark.parametrize("d,n,ranks", [
+    (1, [4], [1, 1]),                 # d < 2
+    (2, [4, 4], [2, 3, 1]),           # r_0 != 1
+    (2, [4, 4], [1, 3, 2]),           # r_d != 1
+    (2, [0, 4], [1, 3, 1]),           # n < 1
+    (3, [4, 4, 4], [1, 0, 2, 1]),     # zero rank
+])
+def test_malformed_views_rejected(d, n, ranks):
+    import paper_2511_03598_amd as ttr
+    L = ttr.lib()
+    v, keep = _view(d, n, ranks, [1] * max(d, 1))
+    cap = (ctypes.c_int64 * 4)()
+    assert L.tt_out_capacity(ctypes.byref(v), None, cap) == ttr.TTError(-1, "").status
+    assert L.tt_last_error()
+
+
+def test_round_entry_points_validate_before_device():
+    import paper_2511_03598_amd as ttr
+    L = ttr.lib()
+    v, keep = _view(2, [4, 4], [1, 3, 1], [1, 2])
+    out = ttr._Out(2, (ctypes.c_int64 * 3)(), (ctypes.c_void_p * 2)(1, 2), (ctypes.c_int64 * 2)(100, 100), 0)
+    assert L.tt_round_fixed(ctypes.byref(v), None, 0, 1, None, ctypes.byref(out)) == -1   # ell < 1
+    assert L.tt_round_adaptive(ctypes.byref(v), 0.0, 4, 1, None, ctypes.byref(out)) == -1  # tol <= 0
+    assert L.tt_round_adaptive(ctypes.byref(v), -1.0, 4, 1, None, ctypes.byref(out)) == -1
+    bad = ttr._Out(3, (ctypes.c_int64 * 4)(), (ctypes.c_void_p * 3)(1, 2, 3), (ctypes.c_int64 * 3)(1, 1, 1), 0)
+    assert L.tt_round_adaptive(ctypes.byref(v), 1e-3, 4, 1, None, ctypes.byref(bad)) == -1  # d mismatch
+    assert L.tt_round_fixed(None, None, 4, 1, None, ctypes.byref(out)) == -1
+    nul, keep2 = _view(2, [4, 4], [1, 3, 1], [1, 0])
+    assert L.tt_round_fixed(ctypes.byref(nul), None, 4, 1, None, ctypes.byref(out)) == -1  # null core
+    opts = ttr._Opts(7, 0.0, 0.0, 0, None)
+    assert L.tt_round_fixed(ctypes.byref(v), None, 4, 1, ctypes.byref(opts), ctypes.byref(out)) == -6
+    assert b"F32" in L.tt_last_error()
+
+
+def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
+    import paper_2511_03598_amd as ttr
+    monkeypatch.setattr(ttr, "LIB_PATH", str(tmp_path / "missing.so"))
+    monkeypatch.setattr(ttr, "_lib", None)
+    with pytest.raises(RuntimeError, match="no fallback"):
+        ttr.lib()

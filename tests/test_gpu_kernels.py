@@ -1,0 +1,123 @@
+"""GPU kernel parity against the CPU oracle: the device Philox generator
+(bitwise on the known-answer vectors and on the oracle's words), the
+Gaussian mode factors, the KRP partial contractions in FP64 and FP32, and
+the thin QR."""
+import numpy as np
+import pytest
+
+import ttgen
+from oracle import krp, philox
+from tests.gpu_helpers import say, to_dev
+from tests.test_oracle_philox import load_kat
+
+pytestmark = pytest.mark.gpu
+
+
+def test_device_info(lib):
+    import torch
+    p = torch.cuda.get_device_properties(0)
+    say("device:", p.name, getattr(p, "gcnArchName", "?"), "CUs", p.multi_processor_count)
+
+
+def test_philox_device_kat(lib):
+    import torch
+    rows = load_kat()
+    ctr = torch.tensor(np.array([r[0] for r in rows], dtype=np.uint32).view(np.int32), device="cuda")
+    key = torch.tensor(np.array([r[1] for r in rows], dtype=np.uint32).view(np.int32), device="cuda")
+    out = lib.philox4x32_10(ctr, key).cpu().numpy().view(np.uint32)
+    assert out.tolist() == [r[2] for r in rows]
+
+
+def test_philox_device_matches_oracle_words(lib):
+    import torch
+    rng = np.random.default_rng(5)
+    ctr = rng.integers(0, 2 ** 32, size=(4096, 4), dtype=np.uint64).astype(np.uint32)
+    key = rng.integers(0, 2 ** 32, size=(4096, 2), dtype=np.uint64).astype(np.uint32)
+    got = lib.philox4x32_10(torch.tensor(ctr.view(np.int32), device="cuda"),
+                            torch.tensor(key.view(np.int32), device="cuda")).cpu().numpy().view(np.uint32)
+    assert np.array_equal(got, philox.philox4x32_10(ctr, key))
+
+
+@pytest.mark.parametrize("seed,mode,n,col0,ncols", [(42, 2, 10, 0, 12), (7, 5, 1, 3, 5),
+                                                    (2 ** 40 + 3, 20, 64, 17, 60), (1, 3, 257, 0, 64)])
+def test_gaussian_factor_matches_oracle(lib, seed, mode, n, col0, ncols):
+    got = lib.gaussian_factor(seed, mode, n, col0, ncols).cpu().numpy()
+    ref = philox.gaussian_factor(seed, mode, n, col0, ncols)
+    # same Philox words; log/sin/cos from different math libraries (few ulp)
+    assert np.max(np.abs(got - ref)) <= 1e-14 * max(1.0, np.max(np.abs(ref)))
+
+
+def _pc_case(x, seed, col0, ncols, t, prec, tol):
+    import torch
+    d = len(x)
+    dims = [c.shape[1] for c in x]
+    om = krp.draw_omegas(seed, dims, range(t, d + 1), col0, ncols)
+    ref = krp.partial_contractions_rl(x, om, t)
+    got = lib_pc(x, seed, col0, ncols, t, prec)
+    for k in range(t, d + 1):
+        g = got[k - t]
+        r = ref[k]
+        err = np.linalg.norm(g - r, axis=0) / np.maximum(np.linalg.norm(r, axis=0), 1e-300)
+        assert np.max(err) <= tol, (k, np.max(err))
+
+
+def lib_pc(x, seed, col0, ncols, t, prec):
+    import paper_2511_03598_amd as ttr
+    return [w.cpu().numpy() for w in ttr.partial_contractions(to_dev(x), seed, col0, ncols, t, prec)]
+
+
+@pytest.mark.parametrize("prec,tol", [("f64", 1e-12), ("f32", 1e-5)])
+def test_partial_contractions_c1(lib, prec, tol):
+    say("pc C1", prec)
+    _pc_case(ttgen.c1(), 42, 0, 12, 2, prec, tol)
+
+
+@pytest.mark.parametrize("prec,tol", [("f64", 1e-12), ("f32", 2e-5)])
+def test_partial_contractions_ragged(lib, prec, tol):
+    """Sizes that are not multiples of the tiles: n=70 (two row chunks with
+    a tail), r=37, 130 columns (three column blocks), a later pass (t=3,
+    col0=9)."""
+    say("pc ragged", prec)
+    x = ttgen.small_random(11, 4, [5, 70, 3, 9], [7, 37, 6])
+    _pc_case(x, 3, 0, 130, 2, prec, tol)
+    _pc_case(x, 3, 9, 5, 3, prec, tol)
+
+
+def test_partial_contractions_chunk_invariant_bitwise(lib):
+    """A column is the same bits whichever pass produces it."""
+    x = ttgen.small_random(12, 5, 6, 8)
+    a = lib_pc(x, 9, 0, 20, 2, "f64")
+    b = lib_pc(x, 9, 12, 8, 2, "f64")
+    for wa, wb in zip(a, b):
+        assert np.array_equal(wa[:, 12:20], wb)
+
+
+@pytest.mark.parametrize("prec,tol", [("f64", 1e-12), ("f32", 1e-5)])
+def test_partial_contractions_c2_full_size(lib, prec, tol):
+    """The benchmark's workload (d=20, n=64, formal ranks 200, ell=60)."""
+    say("pc C2 full", prec)
+    _pc_case(ttgen.c2(), 42, 0, 60, 2, prec, tol)
+
+
+@pytest.mark.parametrize("m,b", [(10, 3), (120, 12), (64, 64), (129, 64), (3840, 60), (1000, 17),
+                                 (5000, 1), (20000, 16)])
+def test_qr_matches_householder(lib, m, b):
+    import torch
+    say("qr", m, b)
+    rng = np.random.default_rng(m * 100 + b)
+    a = rng.standard_normal((m, b)) * (10.0 ** (-np.arange(b) / 8.0))[None, :]
+    q = lib.qr(torch.tensor(a, device="cuda")).cpu().numpy()
+    ref = krp.qr_pos(a)
+    assert np.max(np.abs(q.T @ q - np.eye(b))) < 1e-13
+    assert np.max(np.abs(q - ref)) < 1e-11
+
+
+def test_qr_rank_deficient_still_orthonormal(lib):
+    import torch
+    rng = np.random.default_rng(3)
+    a = rng.standard_normal((300, 10)) @ rng.standard_normal((10, 24))  # rank 10, 24 columns
+    q = lib.qr(torch.tensor(a, device="cuda")).cpu().numpy()
+    assert np.max(np.abs(q.T @ q - np.eye(24))) < 1e-12
+    # the leading 10 columns span range(a)
+    p = q[:, :10] @ (q[:, :10].T @ a)
+    assert np.linalg.norm(a - p) < 1e-12 * np.linalg.norm(a)

@@ -1,0 +1,146 @@
+"""End-to-end parity of the GPU roundings (through the C ABI) with the CPU
+oracle run on the same inputs and the same Gaussian factors.
+
+Bar: ||Y_gpu - Y_oracle|| / ||X|| <= 1e-10 with FP64 partial contractions
+and <= 1e-5 with FP32 ones (stable formal-difference norm), equal ranks
+(adaptive decisions within 1e-6 of tau are tie-aware), orthonormality of
+the output cores, and bitwise determinism across runs."""
+import numpy as np
+import pytest
+
+import ttgen
+from oracle import krp, tt, ttsvd
+from tests.gpu_helpers import rel_tensor_diff, say, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"f64": 1e-10, "f32": 1e-5}
+
+
+def _fixed(lib, x, ell, seed, target=None, prec="f64"):
+    y, info = lib.round_fixed(to_dev(x), ell, seed, target_ranks=target, prec=prec)
+    return to_host(y), info
+
+
+def _check_orth(y, info):
+    if info["orth"] == 1:
+        assert tt.left_orth_defect(y) < 1e-12
+    else:
+        assert tt.right_orth_defect(y) < 1e-12
+
+
+@pytest.mark.parametrize("ell", [10, 12])
+def test_fixed_c1(lib, ell):
+    say("fixed C1 ell", ell)
+    x = ttgen.c1()
+    yg, ig = _fixed(lib, x, ell, 42)
+    yo, io = krp.round_fixed(x, ell, 42)
+    assert ig["ranks"] == io["ranks"]
+    assert rel_tensor_diff(x, yg, yo) <= TOL["f64"]
+    assert tt.rel_err(x, yg) < 1e-13  # exact recovery (true ranks 10)
+    _check_orth(yg, ig)
+
+
+def test_fixed_c1_truncated_to_true_ranks(lib):
+    x = ttgen.c1()
+    tgt = [1] + [10] * 5 + [1]
+    yg, ig = _fixed(lib, x, 12, 42, tgt)
+    yo, io = krp.round_fixed(x, 12, 42, tgt)
+    assert ig["ranks"] == io["ranks"] == tgt
+    assert ig["orth"] == 2
+    assert rel_tensor_diff(x, yg, yo) <= TOL["f64"]
+    _check_orth(yg, ig)
+
+
+@pytest.mark.parametrize("case", [
+    dict(seed=21, d=2, n=[30, 25], r=[12], ell=7),
+    dict(seed=22, d=3, n=[1, 5, 4], r=[1, 4], ell=3),          # n=1 mode, rank-1 bond
+    dict(seed=23, d=4, n=[3, 2, 3, 2], r=[3, 6, 2], ell=9),     # ell above every cap
+    dict(seed=24, d=5, n=[7, 70, 3, 9, 4], r=[7, 37, 20, 4], ell=30),
+])
+def test_fixed_edge_shapes(lib, case):
+    say("fixed edge", case)
+    x = ttgen.small_random(case["seed"], case["d"], case["n"], case["r"])
+    yg, ig = _fixed(lib, x, case["ell"], 5)
+    yo, io = krp.round_fixed(x, case["ell"], 5)
+    assert ig["ranks"] == io["ranks"]
+    assert rel_tensor_diff(x, yg, yo) <= TOL["f64"]
+    _check_orth(yg, ig)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_fixed_c2_full_size(lib, prec):
+    """The benchmark workload: d=20, n=64, formal ranks 200, ell=60,
+    target ranks 50 (sketch then right-to-left truncation)."""
+    say("fixed C2", prec)
+    x = ttgen.c2()
+    tgt = [1] + [50] * 19 + [1]
+    yg, ig = _fixed(lib, x, 60, 42, tgt, prec)
+    yo, io = krp.round_fixed(x, 60, 42, tgt)
+    assert ig["ranks"] == io["ranks"]
+    d = rel_tensor_diff(x, yg, yo)
+    say("  rel diff vs oracle", d, "rel err vs X", tt.rel_err(x, yg))
+    assert d <= TOL[prec]
+    _check_orth(yg, ig)
+
+
+def _ranks_equal_or_tie(ig, io, rg, ro):
+    if rg == ro:
+        return True
+    return min(ig["min_margin"], io["min_margin"]) < 1e-6
+
+
+@pytest.mark.parametrize("recompress", [0, 1])
+def test_adaptive_c1(lib, recompress):
+    say("adaptive C1 recompress", recompress)
+    x = ttgen.c1()
+    yg, ig = lib.round_adaptive(to_dev(x), 1e-8, 4, 42, recompress=recompress)
+    yg = to_host(yg)
+    yo, io = krp.round_adaptive(x, 1e-8, 4, 42, recompress=recompress)
+    assert abs(ig["nrmx"] - io["nrmx"]) <= 1e-12 * io["nrmx"]
+    assert _ranks_equal_or_tie(ig, io, ig["ranks"], io["ranks"])
+    assert rel_tensor_diff(x, yg, yo) <= TOL["f64"]
+    assert tt.rel_err(x, yg) <= 1e-8
+    if recompress:
+        assert ig["ranks"] == [1, 10, 10, 10, 10, 10, 1]
+    _check_orth(yg, ig)
+
+
+def test_adaptive_given_norm_and_regeneration(lib):
+    """Decaying spectra (C3 recipe, small): many loop iterations and
+    several regeneration passes; nrmx given."""
+    x = ttgen.c3(seed=7, d=6, n=8, r=24, noise_r=6, decay=3.0)
+    nrm = tt.norm(x)
+    for seed in range(3):
+        say("adaptive decaying seed", seed)
+        yg, ig = lib.round_adaptive(to_dev(x), 1e-5, 2, seed, nrmx=nrm)
+        yg = to_host(yg)
+        yo, io = krp.round_adaptive(x, 1e-5, 2, seed, nrmx=nrm)
+        assert ig["passes"] >= 2
+        assert _ranks_equal_or_tie(ig, io, ig["ranks"], io["ranks"])
+        if ig["ranks"] == io["ranks"]:
+            assert rel_tensor_diff(x, yg, yo) <= TOL["f64"]
+        _check_orth(yg, ig)
+
+
+def test_adaptive_d2_edge(lib):
+    x = ttgen.small_random(31, 2, [9, 40], [9])
+    yg, ig = lib.round_adaptive(to_dev(x), 1e-3, 3, 1)
+    yo, io = krp.round_adaptive(x, 1e-3, 3, 1)
+    assert _ranks_equal_or_tie(ig, io, ig["ranks"], io["ranks"])
+    assert rel_tensor_diff(x, to_host(yg), yo) <= TOL["f64"]
+
+
+def test_deterministic_bitwise(lib):
+    x = to_dev(ttgen.c1())
+    a, _ = lib.round_adaptive(x, 1e-8, 4, 42, recompress=1)
+    b, _ = lib.round_adaptive(x, 1e-8, 4, 42, recompress=1)
+    assert all(np.array_equal(p, q) for p, q in zip(to_host(a), to_host(b)))
+
+
+def test_errors_from_device_calls(lib):
+    x = to_dev(ttgen.c1())
+    with pytest.raises(lib.TTError):
+        lib.round_fixed(x, 0, 1)
+    with pytest.raises(lib.TTError):
+        lib.round_adaptive(x, -1.0, 4, 1)
