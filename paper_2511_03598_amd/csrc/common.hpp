@@ -35,14 +35,20 @@ inline int ceil_div(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
 
 // ---- MFMA wrappers -------------------------------------------------------
 // v_mfma_f64_16x16x4_f64: lane l supplies A[l%16][l/16] and B[l/16][l%16];
-// accumulator element v of lane l is C[4*(l/16)+v][l%16].
+// accumulator element v of lane l is C[(l/16) + 4*v][l%16] (rows interleave
+// across the four lane groups; checked on gfx950 with one-hot operands).
 __device__ __forceinline__ double4_t mfma_f64_16x16x4(double a, double b, double4_t c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
-// v_mfma_f32_16x16x4_f32: same operand/accumulator layout in float32.
+// v_mfma_f32_16x16x4_f32: same operand layout; accumulator element v of
+// lane l is C[4*(l/16) + v][l%16] (four consecutive rows per lane group).
 __device__ __forceinline__ float4_t mfma_f32_16x16x4(float a, float b, float4_t c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
+
+// Row of accumulator element v held by lane group g = l/16.
+__device__ __forceinline__ int mfma_row_f64(int g, int v) { return g + 4 * v; }
+__device__ __forceinline__ int mfma_row_f32(int g, int v) { return 4 * g + v; }
 
 // ---- wave reductions (full 64-lane butterflies) --------------------------
 __device__ __forceinline__ double wave_sum(double v) {

@@ -154,7 +154,7 @@ __global__ void __launch_bounds__(256) gemm_kernel(GemmArgs g, int kchunk, doubl
         for (int j = 0; j < 2; ++j) {
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const int row = m0 + wm + i * 16 + 4 * lg + v;
+                const int row = m0 + wm + i * 16 + mfma_row_f64(lg, v);
                 const int col = n0 + wn + j * 16 + li;
                 if (row < g.M && col < g.N) {
                     if (split) {

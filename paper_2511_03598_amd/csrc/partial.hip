@@ -26,6 +26,7 @@ struct Acc<double> {
     static __device__ __forceinline__ type mma(double a, double b, type c) {
         return mfma_f64_16x16x4(a, b, c);
     }
+    static __device__ __forceinline__ int row(int g, int v) { return mfma_row_f64(g, v); }
 };
 template <>
 struct Acc<float> {
@@ -33,6 +34,7 @@ struct Acc<float> {
     static __device__ __forceinline__ type mma(float a, float b, type c) {
         return mfma_f32_16x16x4(a, b, c);
     }
+    static __device__ __forceinline__ int row(int g, int v) { return mfma_row_f32(g, v); }
 };
 
 template <typename T, bool SCALED>
@@ -110,7 +112,7 @@ __global__ void __launch_bounds__(256) pc_kernel(PcArgs p) {
         for (int mb = 0; mb < 4; ++mb) {
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const int i = rc + mb * 16 + 4 * lg + v;
+                const int i = rc + mb * 16 + Acc<T>::row(lg, v);
                 if (i < n) {
                     const double* orow = p.Om + (size_t)i * p.ldo + colbase;
 #pragma unroll
