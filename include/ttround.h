@@ -159,6 +159,16 @@ tt_status tt_partial_contractions(const tt_view* x, uint64_t seed, int64_t col0,
  * same routine the rounding uses for its sketches. */
 tt_status tt_qr(double* a, int64_t m, int64_t b, void* stream);
 
+/* SVD of a small p x q column-major float64 device matrix a (ld = p),
+ * p >= q, 1 <= q <= 64, by one-sided Jacobi (the truncated SVD of the
+ * right-to-left truncation pass, Remark 2).  Writes g = A V (p x q, ld p,
+ * columns sorted by decreasing norm, i.e. U Sigma), v (q x q, ld q) and
+ * sig[q]; *t_out (host) receives the kept rank: the smallest t >= 1 whose
+ * tail sqrt(sum_{j>=t} sig_j^2) <= tau when tau >= 0, else
+ * min(max(target, 1), q).  All arrays are device memory. */
+tt_status tt_svd_small(const double* a, int64_t p, int64_t q, double* g, double* v, double* sig,
+                       double tau, int64_t target, int64_t* t_out, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -13,7 +13,7 @@ import ctypes
 import os
 
 __all__ = ["lib", "round_fixed", "round_adaptive", "gaussian_factor", "philox4x32_10",
-           "partial_contractions", "qr", "out_capacity", "last_info", "TTError",
+           "partial_contractions", "qr", "svd_small", "out_capacity", "last_info", "TTError",
            "PREC_F64", "PREC_F32", "PREC_BF16", "LIB_PATH"]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libttround.so")
@@ -77,6 +77,7 @@ def lib():
             "tt_philox4x32_10": [vp, vp, vp, i64, vp],
             "tt_partial_contractions": [P(_View), u64, i64, i64, i32, ctypes.c_int, P(vp), vp],
             "tt_qr": [vp, i64, i64, vp],
+            "tt_svd_small": [vp, i64, i64, vp, vp, vp, dbl, i64, P(i64), vp],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -218,6 +219,23 @@ def partial_contractions(cores, seed, col0, ncols, t=2, prec="f64", stream=None)
     _check(lib().tt_partial_contractions(ctypes.byref(h.view), ctypes.c_uint64(seed), int(col0),
                                          int(ncols), int(t), _PREC[prec], arr, _stream(stream)))
     return ws
+
+
+def svd_small(a, tau=-1.0, target=0, stream=None):
+    """One-sided Jacobi SVD of a (p x q) float64 CUDA tensor, p >= q <= 64.
+    Returns (G = U Sigma sorted, V, sigma, kept rank t)."""
+    torch = _torch()
+    p, q = a.shape
+    buf = a.t().contiguous()
+    g = torch.empty((q, p), dtype=torch.float64, device=a.device)
+    v = torch.empty((q, q), dtype=torch.float64, device=a.device)
+    sig = torch.empty(q, dtype=torch.float64, device=a.device)
+    t = ctypes.c_int64()
+    _check(lib().tt_svd_small(ctypes.c_void_p(buf.data_ptr()), int(p), int(q),
+                              ctypes.c_void_p(g.data_ptr()), ctypes.c_void_p(v.data_ptr()),
+                              ctypes.c_void_p(sig.data_ptr()), float(tau), int(target),
+                              ctypes.byref(t), _stream(stream)))
+    return g.t(), v.t(), sig, int(t.value)
 
 
 def qr(a, stream=None):

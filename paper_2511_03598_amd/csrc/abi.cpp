@@ -169,4 +169,12 @@ tt_status tt_qr(double* a, int64_t m, int64_t b, void* stream) {
     return guarded([&] { ttr::qr_inplace(a, m, b, (hipStream_t)stream); });
 }
 
+tt_status tt_svd_small(const double* a, int64_t p, int64_t q, double* g, double* v, double* sig,
+                       double tau, int64_t target, int64_t* t_out, void* stream) {
+    return guarded([&] {
+        if (!t_out) throw ttr::Error(TT_EINVAL, "null t_out");
+        *t_out = ttr::svd_small(a, p, q, g, v, sig, tau, target, (hipStream_t)stream);
+    });
+}
+
 }  // extern "C"

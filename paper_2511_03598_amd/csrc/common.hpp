@@ -11,6 +11,7 @@
 namespace ttr {
 
 typedef double double4_t __attribute__((ext_vector_type(4)));
+typedef double double2_t __attribute__((ext_vector_type(2)));
 typedef float float4_t __attribute__((ext_vector_type(4)));
 
 constexpr int kWave = 64;
@@ -61,10 +62,21 @@ __device__ __forceinline__ float wave_sum(float v) {
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
     return v;
 }
-// Sum over the 16 lanes of a quarter-wave group (lanes 16g..16g+15).
+// DPP move of a double (two 32-bit halves) with a constant control word.
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xF, 0xF, true);
+    return __hiloint2double(hi, lo);
+}
+// Sum over the 16 lanes of a DPP row (lanes 16g..16g+15), result in every
+// lane: swap neighbours, swap pairs (quad_perm), then fold the row with
+// row_half_mirror and row_mirror.  All 16 lanes must be active.
 __device__ __forceinline__ double group16_sum(double v) {
-#pragma unroll
-    for (int off = 8; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+    v += dpp_f64<0xB1>(v);   // quad_perm [1,0,3,2]
+    v += dpp_f64<0x4E>(v);   // quad_perm [2,3,0,1]
+    v += dpp_f64<0x141>(v);  // row_half_mirror
+    v += dpp_f64<0x140>(v);  // row_mirror
     return v;
 }
 __device__ __forceinline__ int wave_max_int(int v) {

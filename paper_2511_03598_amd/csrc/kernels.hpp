@@ -92,6 +92,13 @@ size_t qr_workspace_doubles(const QrPlan& p);
 // `ws` holds qr_workspace_doubles(p) doubles, `counters` p.nodes zeroed ints
 // (they are left zeroed on return).
 void launch_qr(const QrPlan& p, double* a, double* r_out, double* ws, int* counters,
+               hipStream_t s, const int* only_if = nullptr);
+// CholeskyQR2 / shifted CholeskyQR3 fast path (qr_chol.hip), b <= 64,
+// m >= b.  flags[0] is set to 1 when a pass breaks down (rank-deficient
+// panel), in which case `a` is left untouched for the Householder path
+// (launch_qr with only_if=flags); flags[1] records the shifted route.
+size_t cq_workspace_doubles(int m, int b);
+void launch_cq(double* a, int m, int b, int lda, double* r_out, double* ws, int* flags,
                hipStream_t s);
 
 // ---- small SVD by one-sided Jacobi (svd.hip) -------------------------------

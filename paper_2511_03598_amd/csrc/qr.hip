@@ -85,6 +85,7 @@ struct QrDev {
     double* rbuf;   // nodes x b x b (column-major)
     double* vnode;  // (nodes - P) x (2b x b)
     int* cnt;       // nodes
+    const int* only_if;  // if set, run only when *only_if != 0
 };
 
 __device__ __forceinline__ int level_count(int P, int level) {
@@ -111,6 +112,7 @@ __device__ void write_r(const QrDev& q, const double* L, int ld, int node) {
 }
 
 __global__ void __launch_bounds__(256) qr_factor_kernel(QrDev q) {
+    if (q.only_if != nullptr && *q.only_if == 0) return;
     extern __shared__ double lds[];
     __shared__ double red[4];
     __shared__ double tau_s[64];
@@ -191,6 +193,7 @@ __global__ void __launch_bounds__(256) qr_factor_kernel(QrDev q) {
 }
 
 __global__ void __launch_bounds__(256) qr_formq_kernel(QrDev q, int nodes) {
+    if (q.only_if != nullptr && *q.only_if == 0) return;
     extern __shared__ double lds[];
     __shared__ double tau_s[64];
     const int b = q.b, leaf = blockIdx.x, hm = q.hmax;
@@ -293,7 +296,7 @@ size_t qr_workspace_doubles(const QrPlan& p) {
 }
 
 void launch_qr(const QrPlan& p, double* a, double* r_out, double* ws, int* counters,
-               hipStream_t s) {
+               hipStream_t s, const int* only_if) {
     static std::once_flag once;
     std::call_once(once, [] {
         const int lim = device_lds_limit() - 2048;
@@ -316,6 +319,7 @@ void launch_qr(const QrPlan& p, double* a, double* r_out, double* ws, int* count
     q.rbuf = ws + (size_t)p.nodes * b;
     q.vnode = q.rbuf + (size_t)p.nodes * b * b;
     q.cnt = counters;
+    q.only_if = only_if;
     const size_t lds_factor = (size_t)p.hmax * b * sizeof(double);
     hipLaunchKernelGGL(qr_factor_kernel, dim3(p.P), dim3(256), lds_factor, s, q);
     TTR_CHECK_LAUNCH();

@@ -16,6 +16,8 @@
 #include <algorithm>
 #include <cmath>
 #include <climits>
+#include <cstdio>
+#include <cstdlib>
 #include <memory>
 #include <mutex>
 
@@ -56,7 +58,7 @@ struct DevBuf {
 
 struct Workspace {
     int device = -1;
-    DevBuf omega, w, colexp, maxexp, dn, doff, y0, y1, q, sbuf, tbuf, m, qrws, qrcnt, part, scal,
+    DevBuf omega, w, colexp, maxexp, dn, doff, y0, y1, q, sbuf, tbuf, m, qrws, cqws, qrcnt, part, scal,
         sumpart, sumcnt, small1, small2, small3, small4, tint, tmp;
     double* host = nullptr;  // pinned scalars
     int* host_int = nullptr;
@@ -154,13 +156,6 @@ void gemm(Workspace& ws, hipStream_t s, int M, int N, int K, const double* A, in
     launch_gemm(g, splits, partials, s);
 }
 
-void qr(Workspace& ws, hipStream_t s, double* a, int m, int b, int lda, double* r_out = nullptr) {
-    const QrPlan p = plan_qr(m, b, lda);
-    double* w = ws.qrws.as<double>(qr_workspace_doubles(p));
-    int* cnt = ws.qr_counters(p.nodes, s);
-    launch_qr(p, a, r_out, w, cnt, s);
-}
-
 double read_scalar(Workspace& ws, hipStream_t s, const double* dev) {
     TTR_HIP(hipMemcpyAsync(ws.host, dev, sizeof(double), hipMemcpyDeviceToHost, s));
     TTR_HIP(hipStreamSynchronize(s));
@@ -171,6 +166,25 @@ int read_int(Workspace& ws, hipStream_t s, const int* dev) {
     TTR_HIP(hipMemcpyAsync(ws.host_int, dev, sizeof(int), hipMemcpyDeviceToHost, s));
     TTR_HIP(hipStreamSynchronize(s));
     return ws.host_int[0];
+}
+
+// Thin QR: CholeskyQR2 when the panel is certified well conditioned, else
+// (decided on the device) Householder TSQR on the untouched panel.
+void qr(Workspace& ws, hipStream_t s, double* a, int m, int b, int lda, double* r_out = nullptr) {
+    const QrPlan p = plan_qr(m, b, lda);
+    int* cnt = ws.qr_counters(p.nodes + 8, s);
+    int* flags = cnt + p.nodes + 4;  // route flags, set by the fast path
+    double* cw = ws.cqws.as<double>(cq_workspace_doubles(m, b));
+    launch_cq(a, m, b, lda, r_out, cw, flags, s);
+    double* w = ws.qrws.as<double>(qr_workspace_doubles(p));
+    launch_qr(p, a, r_out, w, cnt, s, flags);
+    static const bool trace = std::getenv("TTR_TRACE_QR") != nullptr;
+    if (trace) {
+        const int f = read_int(ws, s, flags);
+        const int sh = read_int(ws, s, flags + 1);
+        std::fprintf(stderr, "ttr qr m=%d b=%d route=%s\n", m, b,
+                     f ? "householder" : (sh ? "shifted-cholqr3" : "cholqr2"));
+    }
 }
 
 double sumsq(Workspace& ws, hipStream_t s, const double* a, int64_t sr, int64_t sc, int rows,
@@ -344,6 +358,10 @@ void recompress(Workspace& ws, hipStream_t st, const Shape& s, double** cores, i
         const int tgt = target ? (int)target[k - 1] : 0;
         launch_svd_jacobi(A, b, b, q, G, Vs, sig, tau, tgt, tdev, st);
         const int t = read_int(ws, st, tdev);
+        static const bool trace = std::getenv("TTR_TRACE_QR") != nullptr;
+        if (trace)
+            std::fprintf(stderr, "ttr svd p=%d q=%d kept=%d sweeps=%d\n", b, q, t,
+                         read_int(ws, st, tdev + 1));
         // New H(Y_k) = V_t^T Q^T (t x m) or V_t^T when m < b.
         if (m >= b) {
             gemm(ws, st, t, m, b, Vs, q, 1, H, m, 1, tmp, m, 1);
@@ -620,6 +638,15 @@ void qr_inplace(double* a, int64_t m, int64_t b, hipStream_t st) {
     WsLease lease;
     qr(*lease.ws, st, a, (int)m, (int)b, (int)m);
     TTR_HIP(hipStreamSynchronize(st));
+}
+
+int64_t svd_small(const double* a, int64_t p, int64_t q, double* g, double* v, double* sig,
+                  double tau, int64_t target, hipStream_t st) {
+    if (!a || !g || !v || !sig || q < 1 || q > 64 || p < q) throw Error(-1, "bad SVD request");
+    WsLease lease;
+    int* tdev = lease->tint.as<int>(16);
+    launch_svd_jacobi(a, (int)p, (int)p, (int)q, g, v, sig, tau, (int)target, tdev, st);
+    return read_int(*lease.ws, st, tdev);
 }
 
 }  // namespace ttr

@@ -3,7 +3,9 @@
 // of the TT-Rounding algorithm, Sec. 2.2, applied to R^T from the LQ of
 // H(Y_k)).  Columns of A are rotated pairwise until mutually orthogonal:
 // A V = U Sigma.  Pairs follow a round-robin tournament, q/2 disjoint pairs
-// per round, each pair owned by a 16-lane group; one barrier per round.
+// per round, each pair owned by a 16-lane group that holds its two columns
+// (4 rows per lane) in registers for the round (DPP reductions); one
+// barrier per round.
 // One-sided Jacobi gives singular values to high relative accuracy, which
 // the tolerance-based truncation needs.
 #include <algorithm>
@@ -17,75 +19,99 @@ __device__ __forceinline__ int rr_player(int pos, int r, int qq) {
     return pos == 0 ? 0 : 1 + ((pos - 1 + r) % (qq - 1));
 }
 
-__global__ void __launch_bounds__(256) svd_jacobi_kernel(const double* A, int lda, int p, int q,
+__global__ void __launch_bounds__(512) svd_jacobi_kernel(const double* A, int lda, int p, int q,
                                                          double* G, double* Vs, double* sig,
                                                          double tau, int target, int* t_out) {
-    extern __shared__ double lds[];
+    // Columns of A and V live in LDS with a fixed stride of 64 rows, zero
+    // padded, so every lane handles exactly 4 rows without masks.
+    constexpr int LD = 64;
+    __shared__ double As[64 * LD];
+    __shared__ double V[64 * LD];
     __shared__ double sg[64];
     __shared__ int perm[64];
     __shared__ int rotated;
-    double* As = lds;          // p x q, ld p
-    double* V = lds + p * q;   // q x q, ld q
-    const int tid = threadIdx.x, g = tid >> 4, l16 = tid & 15;
-    for (int t = tid; t < p * q; t += 256) {
-        const int c = t / p, i = t - c * p;
-        As[t] = A[(size_t)c * lda + i];
+    __shared__ int nsweeps;
+    const int tid = threadIdx.x;
+    for (int t = tid; t < 64 * LD; t += 512) {
+        const int c = t / LD, i = t - c * LD;
+        As[t] = (c < q && i < p) ? A[(size_t)c * lda + i] : 0.0;
+        V[t] = (c == i && c < q) ? 1.0 : 0.0;
     }
-    for (int t = tid; t < q * q; t += 256) V[t] = ((t / q) == (t % q)) ? 1.0 : 0.0;
     const int qq = q + (q & 1);
-    const double tol = fmax(1e-15, 2.3e-16 * (double)p);
+    // Rotate while (x.y)^2 > tol^2 (x.x)(y.y); tol sits well above the
+    // rounding error of a p-term dot product (~p u) so the sweep test can be met.
+    const double tol2 = 1e-26;
+    if (tid == 0) nsweeps = 0;
+    // One column pair per 16-lane group; lane l16 holds rows l16, l16+16, ...
+    const int g8 = tid >> 4, l8 = tid & 15;
+    const bool has_pair = g8 < qq / 2 && qq >= 2;
     __syncthreads();
     for (int sweep = 0; sweep < 60 && qq >= 2; ++sweep) {
         if (tid == 0) rotated = 0;
         __syncthreads();
+        // Round-robin positions g8 and qq-1-g8; players rotate by one per round.
+        int v1 = g8 - 1, v2 = qq - 2 - g8;  // (pos - 1) for the two positions
         for (int r = 0; r < qq - 1; ++r) {
-            for (int ps = g; ps < qq / 2; ps += 16) {
-                int i1 = rr_player(ps, r, qq), i2 = rr_player(qq - 1 - ps, r, qq);
+            int i1 = -1, i2 = -1;
+            if (has_pair) {
+                i1 = (g8 == 0) ? 0 : 1 + v1;
+                i2 = 1 + v2;
                 if (i1 > i2) {
                     const int tmp = i1;
                     i1 = i2;
                     i2 = tmp;
                 }
-                if (i2 >= q) continue;  // bye
+                if (i2 >= q) i1 = -1;  // bye
+            }
+            if (++v1 >= qq - 1) v1 -= qq - 1;
+            if (++v2 >= qq - 1) v2 -= qq - 1;
+            if (i1 >= 0) {
+                double x[4], y[4], vx[4], vy[4];
                 double al = 0.0, be = 0.0, ga = 0.0;
-                for (int i = l16; i < p; i += 16) {
-                    const double x = As[i1 * p + i], y = As[i2 * p + i];
-                    al += x * x;
-                    be += y * y;
-                    ga += x * y;
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    x[t] = As[i1 * LD + l8 + 16 * t];
+                    y[t] = As[i2 * LD + l8 + 16 * t];
+                    vx[t] = V[i1 * LD + l8 + 16 * t];
+                    vy[t] = V[i2 * LD + l8 + 16 * t];
+                }
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    al += x[t] * x[t];
+                    be += y[t] * y[t];
+                    ga += x[t] * y[t];
                 }
                 al = group16_sum(al);
                 be = group16_sum(be);
                 ga = group16_sum(ga);
-                if (ga != 0.0 && fabs(ga) > tol * sqrt(al * be)) {
-                    if (l16 == 0) rotated = 1;
+                if (ga * ga > tol2 * (al * be)) {
+                    if (l8 == 0) rotated = 1;
                     const double zeta = (be - al) / (2.0 * ga);
                     const double t = copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-                    const double c = 1.0 / sqrt(1.0 + t * t), s = c * t;
-                    for (int i = l16; i < p; i += 16) {
-                        const double x = As[i1 * p + i], y = As[i2 * p + i];
-                        As[i1 * p + i] = c * x - s * y;
-                        As[i2 * p + i] = s * x + c * y;
-                    }
-                    for (int i = l16; i < q; i += 16) {
-                        const double x = V[i1 * q + i], y = V[i2 * q + i];
-                        V[i1 * q + i] = c * x - s * y;
-                        V[i2 * q + i] = s * x + c * y;
+                    const double c = rsqrt(1.0 + t * t), sn = c * t;
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        const int i = l8 + 16 * k;
+                        As[i1 * LD + i] = c * x[k] - sn * y[k];
+                        As[i2 * LD + i] = sn * x[k] + c * y[k];
+                        V[i1 * LD + i] = c * vx[k] - sn * vy[k];
+                        V[i2 * LD + i] = sn * vx[k] + c * vy[k];
                     }
                 }
             }
             __syncthreads();
         }
         const int done = !rotated;
+        if (tid == 0) nsweeps = sweep + 1;
         __syncthreads();
         if (done) break;
     }
     // Column norms, sort by decreasing norm (stable by index).
-    for (int c = g; c < q; c += 16) {
+    for (int c = g8; c < q; c += 32) {
         double s = 0.0;
-        for (int i = l16; i < p; i += 16) s += As[c * p + i] * As[c * p + i];
+        for (int i = l8; i < 64; i += 16) s += As[c * 64 + i] * As[c * 64 + i];
         s = group16_sum(s);
-        if (l16 == 0) sg[c] = sqrt(s);
+        if (l8 == 0) sg[c] = sqrt(s);
     }
     __syncthreads();
     if (tid < q) {
@@ -95,13 +121,13 @@ __global__ void __launch_bounds__(256) svd_jacobi_kernel(const double* A, int ld
         perm[rank] = tid;
     }
     __syncthreads();
-    for (int t = tid; t < p * q; t += 256) {
+    for (int t = tid; t < p * q; t += 512) {
         const int r = t / p, i = t - r * p;
-        G[(size_t)r * p + i] = As[perm[r] * p + i];
+        G[(size_t)r * p + i] = As[perm[r] * 64 + i];
     }
-    for (int t = tid; t < q * q; t += 256) {
+    for (int t = tid; t < q * q; t += 512) {
         const int r = t / q, i = t - r * q;
-        Vs[(size_t)r * q + i] = V[perm[r] * q + i];
+        Vs[(size_t)r * q + i] = V[perm[r] * 64 + i];
     }
     if (tid < q) sig[tid] = sg[perm[tid]];
     if (tid == 0) {
@@ -119,7 +145,8 @@ __global__ void __launch_bounds__(256) svd_jacobi_kernel(const double* A, int ld
         } else {
             t = min(max(target, 1), q);
         }
-        *t_out = t;
+        t_out[0] = t;
+        t_out[1] = nsweeps;
     }
 }
 
@@ -127,19 +154,9 @@ __global__ void __launch_bounds__(256) svd_jacobi_kernel(const double* A, int ld
 
 void launch_svd_jacobi(const double* A, int lda, int p, int q, double* G, double* Vs, double* sig,
                        double tau, int target, int* t_out, hipStream_t s) {
-    if (q < 1 || q > 64 || p < q)
-        throw Error(-6, "small SVD: need 1 <= q <= 64 and p >= q");
-    const size_t bytes = (size_t)(p * q + q * q) * sizeof(double);
-    if ((int)bytes > device_lds_limit() - 4096)
-        throw Error(-6, "small SVD: matrix too large for LDS");
-    static bool attr = false;
-    if (!attr) {
-        TTR_HIP(hipFuncSetAttribute((const void*)svd_jacobi_kernel,
-                                    hipFuncAttributeMaxDynamicSharedMemorySize,
-                                    device_lds_limit() - 4096));
-        attr = true;
-    }
-    hipLaunchKernelGGL(svd_jacobi_kernel, dim3(1), dim3(256), bytes, s, A, lda, p, q, G, Vs, sig,
+    if (q < 1 || q > 64 || p < q || p > 64)
+        throw Error(-6, "small SVD: need 1 <= q <= p <= 64");
+    hipLaunchKernelGGL(svd_jacobi_kernel, dim3(1), dim3(512), 0, s, A, lda, p, q, G, Vs, sig,
                        tau, target, t_out);
     TTR_CHECK_LAUNCH();
 }

@@ -121,3 +121,44 @@ def test_qr_rank_deficient_still_orthonormal(lib):
     # the leading 10 columns span range(a)
     p = q[:, :10] @ (q[:, :10].T @ a)
     assert np.linalg.norm(a - p) < 1e-12 * np.linalg.norm(a)
+
+
+def test_qr_ill_conditioned_full_rank_takes_householder_route(lib):
+    """Two nearly parallel columns fail the Cholesky certificate; the panel
+    must still come back as the Householder Q."""
+    import torch
+    rng = np.random.default_rng(8)
+    a = rng.standard_normal((2000, 20))
+    a[:, 19] = a[:, 0] + 1e-9 * rng.standard_normal(2000)
+    q = lib.qr(torch.tensor(a, device="cuda")).cpu().numpy()
+    ref = krp.qr_pos(a)
+    assert np.max(np.abs(q.T @ q - np.eye(20))) < 1e-13
+    assert np.max(np.abs(q[:, :19] - ref[:, :19])) < 1e-12
+    assert np.max(np.abs(q[:, 19] - ref[:, 19])) < 1e-5   # sensitive direction
+
+
+@pytest.mark.parametrize("p,q", [(60, 60), (64, 64), (40, 13), (7, 1), (30, 30)])
+def test_svd_small_matches_lapack(lib, p, q):
+    import torch
+    from oracle.ttsvd import truncation_rank
+    rng = np.random.default_rng(p * 7 + q)
+    a = rng.standard_normal((p, q)) * (10.0 ** (-np.arange(q) / 6.0))[None, :]
+    g, v, sig, t = lib.svd_small(torch.tensor(a, device="cuda"), tau=1e-3)
+    g, v, sig = g.cpu().numpy(), v.cpu().numpy(), sig.cpu().numpy()
+    s_ref = np.linalg.svd(a, compute_uv=False)
+    assert np.max(np.abs(sig - s_ref) / s_ref) < 1e-12          # high relative accuracy
+    assert np.max(np.abs(v.T @ v - np.eye(q))) < 1e-13
+    assert np.linalg.norm(a @ v - g) < 1e-13 * np.linalg.norm(a)
+    assert t == truncation_rank(s_ref, 1e-3)
+    _, _, _, t2 = lib.svd_small(torch.tensor(a, device="cuda"), tau=-1.0, target=5)
+    assert t2 == min(5, q)
+
+
+def test_svd_small_rank_deficient(lib):
+    import torch
+    rng = np.random.default_rng(4)
+    a = rng.standard_normal((50, 6)) @ rng.standard_normal((6, 40))
+    g, v, sig, t = lib.svd_small(torch.tensor(a, device="cuda"), tau=1e-10 * np.linalg.norm(a))
+    sig = sig.cpu().numpy()
+    assert t == 6
+    assert np.all(sig[6:] < 1e-12 * sig[0])
