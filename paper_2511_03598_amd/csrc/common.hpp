@@ -79,6 +79,14 @@ __device__ __forceinline__ double group16_sum(double v) {
     v += dpp_f64<0x140>(v);  // row_mirror
     return v;
 }
+// 1/sqrt(x) for normal positive x: hardware estimate (v_rsq_f64) plus two
+// Newton steps, each of which squares the relative error; a few ulp.
+__device__ __forceinline__ double rsqrt_nr(double x) {
+    double y = __builtin_amdgcn_rsq(x);
+    y = fma(0.5 * y, fma(-(x * y), y, 1.0), y);
+    y = fma(0.5 * y, fma(-(x * y), y, 1.0), y);
+    return y;
+}
 __device__ __forceinline__ int wave_max_int(int v) {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) v = max(v, __shfl_xor(v, off, kWave));

@@ -20,63 +20,61 @@ struct Tile {
     double a[4], b[4];
 };
 
+// Element (k, n) of B as double (FP32 storage scaled by 2^bexp[n] when the
+// sketch is kept in FP32).
+__device__ __forceinline__ double load_b(const GemmArgs& g, size_t off, int n) {
+    if (g.Bf) {
+        const double v = (double)g.Bf[off];
+        return g.bexp ? ldexp(v, g.bexp[n]) : v;
+    }
+    return g.B[off];
+}
+
+// Global -> registers for one K slab.  Indices are clamped into the matrix
+// so every load is issued unconditionally (a masked load serialises on its
+// own wait); out-of-range elements are zeroed afterwards.  The caller
+// guarantees k0 < kend.
 __device__ __forceinline__ void load_tiles(const GemmArgs& g, int m0, int n0, int k0, int kend,
                                            Tile& t) {
     const int tid = threadIdx.x;
     // A: 64 (m) x 16 (k)
     if (g.sak == 1) {
         const int m = tid >> 2, kk = (tid & 3) * 4;
-        const int gm = m0 + m;
+        const int gm = m0 + m, gmc = min(gm, g.M - 1);
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const int gk = k0 + kk + q;
-            t.a[q] = (gm < g.M && gk < kend) ? g.A[(size_t)gm * g.sam + gk] : 0.0;
+            const double v = g.A[(size_t)gmc * g.sam + min(gk, kend - 1)];
+            t.a[q] = (gm < g.M && gk < kend) ? v : 0.0;
         }
     } else {
         const int kk = tid >> 4, m = (tid & 15) * 4;
-        const int gk = k0 + kk;
+        const int gk = k0 + kk, gkc = min(gk, kend - 1);
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const int gm = m0 + m + q;
-            t.a[q] = (gm < g.M && gk < kend) ? g.A[(size_t)gm * g.sam + (size_t)gk * g.sak] : 0.0;
+            const double v = g.A[(size_t)min(gm, g.M - 1) * g.sam + (size_t)gkc * g.sak];
+            t.a[q] = (gm < g.M && gk < kend) ? v : 0.0;
         }
     }
     // B: 16 (k) x 64 (n)
     if (g.sbn == 1 || g.sbk != 1) {
         const int kk = tid >> 4, nn = (tid & 15) * 4;
-        const int gk = k0 + kk;
+        const int gk = k0 + kk, gkc = min(gk, kend - 1);
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            const int gn = n0 + nn + q;
-            double v = 0.0;
-            if (gk < kend && gn < g.N) {
-                const size_t off = (size_t)gk * g.sbk + (size_t)gn * g.sbn;
-                if (g.Bf) {
-                    v = (double)g.Bf[off];
-                    if (g.bexp) v = ldexp(v, g.bexp[gn]);
-                } else {
-                    v = g.B[off];
-                }
-            }
-            t.b[q] = v;
+            const int gn = n0 + nn + q, gnc = min(gn, g.N - 1);
+            const double v = load_b(g, (size_t)gkc * g.sbk + (size_t)gnc * g.sbn, gnc);
+            t.b[q] = (gk < kend && gn < g.N) ? v : 0.0;
         }
     } else {
         const int nn = tid >> 2, kk = (tid & 3) * 4;
-        const int gn = n0 + nn;
+        const int gn = n0 + nn, gnc = min(gn, g.N - 1);
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const int gk = k0 + kk + q;
-            double v = 0.0;
-            if (gk < kend && gn < g.N) {
-                const size_t off = (size_t)gk + (size_t)gn * g.sbn;
-                if (g.Bf) {
-                    v = (double)g.Bf[off];
-                    if (g.bexp) v = ldexp(v, g.bexp[gn]);
-                } else {
-                    v = g.B[off];
-                }
-            }
-            t.b[q] = v;
+            const double v = load_b(g, (size_t)min(gk, kend - 1) + (size_t)gnc * g.sbn, gnc);
+            t.b[q] = (gk < kend && gn < g.N) ? v : 0.0;
         }
     }
 }

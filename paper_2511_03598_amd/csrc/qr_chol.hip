@@ -2,8 +2,9 @@
 // ill-conditioned panels, all decided on the device.
 //
 //   gram    : per-block partial Grams G = S^T S (MFMA), written to a buffer;
-//   chol    : one wave sums the partials in a fixed order, factors
-//             G = R^T R (Cholesky), forms R^{-1} and sets the route flags;
+//   chol    : one workgroup sums the partials in a fixed order, factors
+//             G = R^T R (Cholesky), forms R^{-1} in the same sweep and sets
+//             the route flags;
 //   apply   : Q_next = Q_prev R^{-1} per row block (MFMA), plus the partial
 //             Grams of Q_next when another pass follows.
 //
@@ -35,8 +36,8 @@ struct CqDev {
     double* q1;     // m x b temporaries (ld m)
     double* q2;
     double* gpart;  // P x 64 x 64 partial Grams
-    double* rinv;   // 3 x 64 x 64 (one per pass)
-    double* rfac;   // 3 x 64 x 64
+    double* rinv;   // 3 x 64 x 64 R^{-1} per pass (row-major, identity-padded)
+    double* rfac;   // 3 x 64 x 64 R per pass
     double* r_out;  // optional b x b column-major R of the panel
     int* flags;
 };
@@ -60,12 +61,25 @@ __device__ __forceinline__ void gram_tile(const double* T, double4_t acc[4]) {
     }
 }
 
+// T (TB rows x 64 cols, zero padded) <- rows [r, r_end) of the column-major
+// panel.  Indices are clamped so every load is issued unconditionally (a
+// masked load would serialise on its own wait); the padding is selected
+// afterwards.  256 threads, 16 loads each.
 __device__ __forceinline__ void load_tile(const double* src, int ld, int r, int r_end, int b,
                                           double* T) {
-    for (int t = threadIdx.x; t < TB * 64; t += blockDim.x) {
-        const int c = t / TB, i = t - c * TB;
-        const int row = r + i;
-        T[i * LDT + c] = (c < b && row < r_end) ? src[(size_t)c * ld + row] : 0.0;
+    const int i = threadIdx.x & (TB - 1), c0 = threadIdx.x / TB;
+    const int row = min(r + i, r_end - 1);
+    double v[16];
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+        const int c = min(c0 + 4 * e, b - 1);
+        v[e] = src[(size_t)c * ld + row];
+    }
+    const bool row_ok = (r + i) < r_end;
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+        const int c = c0 + 4 * e;
+        T[i * LDT + c] = (row_ok && c < b) ? v[e] : 0.0;
     }
 }
 
@@ -97,152 +111,159 @@ __global__ void __launch_bounds__(256) cq_gram_kernel(CqDev q) {
     store_partial(q.gpart + (size_t)blockIdx.x * 4096, acc);
 }
 
-// Cholesky G = R^T R of the LDS matrix G (64 x LDT, identity-padded beyond
-// b, `shift` added to the first b diagonal entries), 256 threads: four lanes
-// share row i = tid/4, each keeping 16 columns in registers (the unrolled
-// step loop keeps register indices static).  At step k the owners of column
-// k publish it through LDS (double-buffered, one barrier per step); every
-// lane forms L(i,k) = G(i,k)/sqrt(G(k,k)) and updates its columns j > k:
-// G(i,j) -= L(i,k) L(j,k).  R (row-major, zero below the diagonal) is
-// written to R.  Returns 1 (block-wide) if a pivot falls to <= rel * (its
-// original value) or is not finite.
-__device__ int chol_quad(const double* G, double shift, double rel, int b, double* R,
-                         double* colbuf) {
-    const int tid = threadIdx.x, i = tid >> 2, qd = tid & 3;
+// Cholesky G = R^T R of the LDS matrix G0 (64 x LDT, identity-padded beyond
+// b, `shift` added to the first b diagonal entries) together with R^{-1},
+// 512 threads.  Lane i of every wave is row i.  Waves 0-3 hold columns
+// 16w .. 16w+15 of G; waves 4-7 hold the same columns of an identity matrix
+// A that the elimination turns into L^{-1} (L = R^T), so R^{-1} = (L^{-1})^T
+// comes out of the same sweep.  Step k (k < b; padding steps are no-ops):
+//   - wave k/16 publishes column k of G, lane k of each A wave publishes its
+//     part of row k of A (double-buffered LDS, one barrier per step);
+//   - L(i,k) = G(i,k)/sqrt(G(k,k)); G waves right of the pivot update their
+//     columns j > k: G(i,j) -= L(i,k) L(j,k) (the column test is static
+//     within the unrolled block, waves left of the pivot are done and skip);
+//   - A waves: row k becomes A_k / L(k,k) and rows i > k lose L(i,k) times it.
+// Rows above the pivot keep stale values in the upper triangle of G, which
+// the factor never reads.  Writes R (row-major, identity-padded) to rfac and
+// R^{-1} to rinv.  Returns 1 (block-wide) if a pivot falls to <= rel * (its
+// original value) or is not finite; the owner of the diagonal checks it.
+__device__ int chol_inv(const double* G0, double shift, double rel, int b, double* colbuf,
+                        double* rowbuf, double* rfac, double* rinv) {
+    const int tid = threadIdx.x, i = tid & 63, w = tid >> 6;
+    const bool gw = w < 4;
+    const int cb0 = 16 * (w & 3);  // first column of this wave's block
     double g[16];
 #pragma unroll
     for (int jj = 0; jj < 16; ++jj) {
-        const int j = 16 * qd + jj;
-        g[jj] = G[i * LDT + j] + ((i == j && i < b) ? shift : 0.0);
+        const int j = cb0 + jj;
+        g[jj] = gw ? G0[i * LDT + j] + ((i == j && i < b) ? shift : 0.0) : (i == j ? 1.0 : 0.0);
     }
+    const double d0 = G0[i * LDT + i] + (i < b ? shift : 0.0);
     int bad = 0;
+#pragma unroll 1
+    for (int kb = 0; kb < 4; ++kb) {
 #pragma unroll
-    for (int k = 0; k < 64; ++k) {
-        double* cb = colbuf + (k & 1) * 64;
-        if (qd == (k >> 4)) cb[i] = g[k & 15];
-        __syncthreads();
-        const double dkk = cb[k];
-        if (k < b) {
-            const double d0 = G[k * LDT + k] + shift;
-            if (!(d0 > 0.0 && dkk > rel * d0 && dkk < INFINITY)) bad = 1;
+        for (int kk = 0; kk < 16; ++kk) {
+            const int k = 16 * kb + kk;
+            if (k < b) {  // uniform
+                double* cb = colbuf + (kk & 1) * 64;
+                double* rb = rowbuf + (kk & 1) * 64;
+                if (w == kb) cb[i] = g[kk];
+                if (!gw && i == k) {
+                    double2_t* dst = reinterpret_cast<double2_t*>(rb + cb0);
+#pragma unroll
+                    for (int h = 0; h < 8; ++h) dst[h] = double2_t{g[2 * h], g[2 * h + 1]};
+                }
+                __syncthreads();
+                const double dkk = cb[k];
+                const double ci = cb[i];
+                if (gw) {
+                    if (w >= kb) {  // uniform
+                        double cv[16];
+                        const double2_t* src = reinterpret_cast<const double2_t*>(cb + cb0);
+#pragma unroll
+                        for (int h = 0; h < 8; ++h) {
+                            const double2_t v = src[h];
+                            cv[2 * h] = v[0];
+                            cv[2 * h + 1] = v[1];
+                        }
+                        const double rinv_k = rsqrt_nr(fmax(dkk, 1e-300));
+                        const double li = ci * rinv_k;
+                        const double t = li * rinv_k;
+                        if (w > kb) {
+#pragma unroll
+                            for (int jj = 0; jj < 16; ++jj) g[jj] = fma(-t, cv[jj], g[jj]);
+                        } else {
+#pragma unroll
+                            for (int jj = kk + 1; jj < 16; ++jj) g[jj] = fma(-t, cv[jj], g[jj]);
+                            g[kk] = li;
+                            if (i == k && !(d0 > 0.0 && dkk > rel * d0 && dkk < INFINITY)) bad = 1;
+                        }
+                    }
+                } else {
+                    double x[16];
+                    const double2_t* src = reinterpret_cast<const double2_t*>(rb + cb0);
+#pragma unroll
+                    for (int h = 0; h < 8; ++h) {
+                        const double2_t v = src[h];
+                        x[2 * h] = v[0];
+                        x[2 * h + 1] = v[1];
+                    }
+                    const double rinv_k = rsqrt_nr(fmax(dkk, 1e-300));
+                    const double c1 = (i == k) ? rinv_k : 1.0;
+                    const double c2 = (i > k) ? ci * rinv_k * rinv_k : 0.0;
+#pragma unroll
+                    for (int jj = 0; jj < 16; ++jj) g[jj] = fma(-c2, x[jj], g[jj] * c1);
+                }
+            }
         }
-        const double rinv = 1.0 / sqrt(fmax(dkk, 1e-300));
-        const double li = cb[i] * rinv;
-        const double* cj = cb + 16 * qd;
-#pragma unroll
-        for (int jj = 0; jj < 16; ++jj)
-            if (16 * qd + jj > k) g[jj] -= li * (cj[jj] * rinv);
-        if (qd == (k >> 4)) g[k & 15] = li;
     }
+    // R(j, i) = L(i, j) for i >= j; R^{-1}(j, i) = L^{-1}(i, j)
 #pragma unroll
     for (int jj = 0; jj < 16; ++jj) {
-        const int k = 16 * qd + jj;
-        R[k * LDT + i] = (k <= i) ? g[jj] : 0.0;
+        const int j = cb0 + jj;
+        if (gw)
+            rfac[j * 64 + i] = (i >= j) ? g[jj] : 0.0;
+        else
+            rinv[j * 64 + i] = (i >= j) ? g[jj] : 0.0;
     }
     return __syncthreads_or(bad);
 }
 
-// X <- X R^{-1} for the 64 rows of an LDS tile X (row stride LDT), R upper
-// triangular (identity-padded): four lanes share a row (16 columns each);
-// column l is solved by its owner lane, broadcast inside the quad (DPP
-// quad_perm) and eliminated from the later columns.  No barriers inside.
-template <int L>
-__device__ __forceinline__ double quad_bcast(double v) {
-    return dpp_f64<(L) | ((L) << 2) | ((L) << 4) | ((L) << 6)>(v);
-}
-
-__device__ void rsolve_rows(const double* R, double* X) {
-    const int tid = threadIdx.x, r = tid >> 2, qd = tid & 3;
-    double s[16];
-#pragma unroll
-    for (int jj = 0; jj < 16; ++jj) s[jj] = X[r * LDT + 16 * qd + jj];
-#pragma unroll
-    for (int l = 0; l < 64; ++l) {
-        double x = s[l & 15] * (1.0 / R[l * LDT + l]);
-        switch (l >> 4) {
-            case 0: x = quad_bcast<0>(x); break;
-            case 1: x = quad_bcast<1>(x); break;
-            case 2: x = quad_bcast<2>(x); break;
-            default: x = quad_bcast<3>(x); break;
-        }
-        const double* rl = R + l * LDT + 16 * qd;
-#pragma unroll
-        for (int jj = 0; jj < 16; ++jj) s[jj] -= x * rl[jj];
-        if (qd == (l >> 4)) s[l & 15] = x;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int jj = 0; jj < 16; ++jj) X[r * LDT + 16 * qd + jj] = s[jj];
-    __syncthreads();
-}
-
-// One workgroup: sum the P partial Grams (fixed order), Cholesky, R^{-1}.
+// One workgroup: sum the P partial Grams (fixed order), factor, invert.
 //   pass 0: plain Cholesky with the 1e-10 certificate; if it fails, redo it
 //           on G + sI and mark the shifted route;
 //   pass 1: plain Cholesky of Q1^T Q1 (fallback flag on breakdown);
 //   pass 2: only on the shifted route, Cholesky of Q2^T Q2.
-__global__ void __launch_bounds__(256) cq_chol_kernel(CqDev q, int pass) {
+__global__ void __launch_bounds__(512) cq_chol_kernel(CqDev q, int pass) {
     if (q.flags[0]) return;
     if (pass == 2 && !q.flags[1]) return;
     __shared__ double G0[64 * LDT];
-    __shared__ double G[64 * LDT];
+    __shared__ __align__(16) double colbuf[128];
+    __shared__ __align__(16) double rowbuf[128];
     const int tid = threadIdx.x;
     const int b = q.b;
-    // 16 consecutive entries per thread, partials summed in order p = 0..P-1
+    // 8 consecutive entries per thread, partials summed in order p = 0..P-1
     {
-        const int i = tid >> 2, j0 = (tid & 3) * 16;
-        double acc[16];
+        const int i = tid >> 3, j0 = (tid & 7) * 8;
+        const int ic = min(i, b - 1);
+        double acc[8];
 #pragma unroll
-        for (int jj = 0; jj < 16; ++jj) acc[jj] = 0.0;
-        if (i < b) {
-            for (int p = 0; p < q.P; ++p) {
-                const double2_t* src =
-                    reinterpret_cast<const double2_t*>(q.gpart + (size_t)p * 4096 + i * 64 + j0);
+        for (int jj = 0; jj < 8; ++jj) acc[jj] = 0.0;
+#pragma unroll 4
+        for (int p = 0; p < q.P; ++p) {
+            const double2_t* src =
+                reinterpret_cast<const double2_t*>(q.gpart + (size_t)p * 4096 + ic * 64 + j0);
 #pragma unroll
-                for (int v = 0; v < 8; ++v) {
-                    const double2_t x = src[v];
-                    acc[2 * v] += x[0];
-                    acc[2 * v + 1] += x[1];
-                }
+            for (int v = 0; v < 4; ++v) {
+                const double2_t x = src[v];
+                acc[2 * v] += x[0];
+                acc[2 * v + 1] += x[1];
             }
         }
 #pragma unroll
-        for (int jj = 0; jj < 16; ++jj) {
+        for (int jj = 0; jj < 8; ++jj) {
             const int j = j0 + jj;
             G0[i * LDT + j] = (i < b && j < b) ? acc[jj] : ((i == j) ? 1.0 : 0.0);
         }
     }
     __syncthreads();
-    __shared__ double colbuf[128];
-    int bad;
-    if (pass == 0) {
-        bad = chol_quad(G0, 0.0, 1e-10, b, G, colbuf);
-        if (bad) {
-            double tr = 0.0;
-            for (int j = 0; j < b; ++j) tr += G0[j * LDT + j];
-            const double shift =
-                11.0 * ((double)q.m * b + (double)b * (b + 1)) * 1.1102230246251565e-16 * tr;
-            bad = chol_quad(G0, shift, 0.0, b, G, colbuf);
-            if (tid == 0) q.flags[1] = 1;
-        } else if (tid == 0) {
-            q.flags[1] = 0;
-        }
-    } else {
-        bad = chol_quad(G0, 0.0, (pass == 1 && !q.flags[1]) ? 0.5 : 0.0, b, G, colbuf);
-    }
-    // R^{-1} = I R^{-1}: identity rows through the row solver (G0 is free)
-    for (int t = tid; t < 64 * 64; t += 256)
-        G0[(t >> 6) * LDT + (t & 63)] = ((t >> 6) == (t & 63)) ? 1.0 : 0.0;
-    __syncthreads();
-    rsolve_rows(G, G0);
-    double* rinv = q.rinv + (size_t)pass * 4096;
     double* rfac = q.rfac + (size_t)pass * 4096;
-    for (int t = tid; t < 64 * 64; t += 256) {
-        const int r = t >> 6, c = t & 63;
-        const bool in = (r < b && c < b);
-        rinv[t] = in ? G0[r * LDT + c] : 0.0;
-        rfac[t] = in ? G[r * LDT + c] : 0.0;
+    double* rinv = q.rinv + (size_t)pass * 4096;
+    // pass 0 retries once with the shift when the certificate fails
+    double shift = 0.0;
+    double rel = (pass == 0) ? 1e-10 : ((pass == 1 && !q.flags[1]) ? 0.5 : 0.0);
+    int bad;
+#pragma unroll 1
+    for (int attempt = 0;; ++attempt) {
+        bad = chol_inv(G0, shift, rel, b, colbuf, rowbuf, rfac, rinv);
+        if (pass != 0 || !bad || attempt == 1) break;
+        double tr = 0.0;
+        for (int j = 0; j < b; ++j) tr += G0[j * LDT + j];
+        shift = 11.0 * ((double)q.m * b + (double)b * (b + 1)) * 1.1102230246251565e-16 * tr;
+        rel = 0.0;
     }
+    if (pass == 0 && tid == 0) q.flags[1] = (shift > 0.0) ? 1 : 0;
     if (tid == 0 && bad) q.flags[0] = 1;
 }
 
@@ -366,7 +387,7 @@ void launch_cq(double* a, int m, int b, int lda, double* r_out, double* ws, int*
     hipLaunchKernelGGL(cq_gram_kernel, dim3(q.P), dim3(256), 0, s, q);
     TTR_CHECK_LAUNCH();
     for (int pass = 1; pass <= 3; ++pass) {
-        hipLaunchKernelGGL(cq_chol_kernel, dim3(1), dim3(256), 0, s, q, pass - 1);
+        hipLaunchKernelGGL(cq_chol_kernel, dim3(1), dim3(512), 0, s, q, pass - 1);
         TTR_CHECK_LAUNCH();
         hipLaunchKernelGGL(cq_apply_kernel, dim3(q.P), dim3(256), 0, s, q, pass);
         TTR_CHECK_LAUNCH();

@@ -15,8 +15,41 @@
 namespace ttr {
 namespace {
 
-__device__ __forceinline__ int rr_player(int pos, int r, int qq) {
-    return pos == 0 ? 0 : 1 + ((pos - 1 + r) % (qq - 1));
+// Sums over the 16 lanes of a DPP row for three values at once (the three
+// butterflies interleaved so their latencies overlap).
+__device__ __forceinline__ void group16_sum3(double& a, double& b, double& c) {
+    a += dpp_f64<0xB1>(a);
+    b += dpp_f64<0xB1>(b);
+    c += dpp_f64<0xB1>(c);
+    a += dpp_f64<0x4E>(a);
+    b += dpp_f64<0x4E>(b);
+    c += dpp_f64<0x4E>(c);
+    a += dpp_f64<0x141>(a);
+    b += dpp_f64<0x141>(b);
+    c += dpp_f64<0x141>(c);
+    a += dpp_f64<0x140>(a);
+    b += dpp_f64<0x140>(b);
+    c += dpp_f64<0x140>(c);
+}
+
+// Rotation (c, s) that diagonalises [[al, ga], [ga, be]] (ga != 0), the
+// classical Jacobi angle tan = sign(z)/(|z| + sqrt(1 + z^2)), z = (be-al)/(2 ga),
+// rewritten without divisions: with dd = be - al, g2 = 2 ga (both scaled by
+// the same power of two so the larger lies in [1/2, 1)), w = |dd| +
+// sqrt(dd^2 + g2^2) and h = 1/sqrt(w^2 + g2^2): c = w h, s = sign(dd) g2 h.
+// c^2 + s^2 = 1 to the accuracy of h whatever the accuracy of w, so the
+// rotation stays orthogonal; the scaling makes it immune to over/underflow.
+__device__ __forceinline__ void jacobi_cs(double al, double be, double ga, double& c, double& s) {
+    double dd = be - al, g2 = 2.0 * ga;
+    int e;
+    (void)frexp(fmax(fabs(dd), fabs(g2)), &e);
+    dd = ldexp(dd, -e);
+    g2 = ldexp(g2, -e);
+    const double x = fma(dd, dd, g2 * g2);  // [1/4, 2)
+    const double w = fabs(dd) + x * rsqrt_nr(x);
+    const double h = rsqrt_nr(fma(w, w, g2 * g2));  // argument in [1/4, 8)
+    c = w * h;
+    s = copysign(1.0, dd) * g2 * h;
 }
 
 __global__ void __launch_bounds__(512) svd_jacobi_kernel(const double* A, int lda, int p, int q,
@@ -31,12 +64,29 @@ __global__ void __launch_bounds__(512) svd_jacobi_kernel(const double* A, int ld
     __shared__ int perm[64];
     __shared__ int rotated;
     __shared__ int nsweeps;
+    __shared__ double wmax[8];
     const int tid = threadIdx.x;
+    double amax = 0.0;
     for (int t = tid; t < 64 * LD; t += 512) {
         const int c = t / LD, i = t - c * LD;
-        As[t] = (c < q && i < p) ? A[(size_t)c * lda + i] : 0.0;
+        const double a = (c < q && i < p) ? A[(size_t)c * lda + i] : 0.0;
+        As[t] = a;
+        amax = fmax(amax, fabs(a));
         V[t] = (c == i && c < q) ? 1.0 : 0.0;
     }
+    // Scale A by a power of two (exact) so its largest entry lies in [1/2, 1):
+    // squared column norms and their products then neither overflow nor
+    // lose the small columns to underflow.  Undone on G and sigma at the end.
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) amax = fmax(amax, __shfl_xor(amax, off, 64));
+    if ((tid & 63) == 0) wmax[tid >> 6] = amax;
+    __syncthreads();
+    amax = wmax[0];
+#pragma unroll
+    for (int w = 1; w < 8; ++w) amax = fmax(amax, wmax[w]);
+    int sexp = 0;
+    if (amax > 0.0 && amax < INFINITY) (void)frexp(amax, &sexp);
+    for (int t = tid; t < 64 * LD; t += 512) As[t] = ldexp(As[t], -sexp);
     const int qq = q + (q & 1);
     // Rotate while (x.y)^2 > tol^2 (x.x)(y.y); tol sits well above the
     // rounding error of a p-term dot product (~p u) so the sweep test can be met.
@@ -81,14 +131,11 @@ __global__ void __launch_bounds__(512) svd_jacobi_kernel(const double* A, int ld
                     be += y[t] * y[t];
                     ga += x[t] * y[t];
                 }
-                al = group16_sum(al);
-                be = group16_sum(be);
-                ga = group16_sum(ga);
+                group16_sum3(al, be, ga);
                 if (ga * ga > tol2 * (al * be)) {
                     if (l8 == 0) rotated = 1;
-                    const double zeta = (be - al) / (2.0 * ga);
-                    const double t = copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-                    const double c = rsqrt(1.0 + t * t), sn = c * t;
+                    double c, sn;
+                    jacobi_cs(al, be, ga, c, sn);
 #pragma unroll
                     for (int k = 0; k < 4; ++k) {
                         const int i = l8 + 16 * k;
@@ -111,7 +158,7 @@ __global__ void __launch_bounds__(512) svd_jacobi_kernel(const double* A, int ld
         double s = 0.0;
         for (int i = l8; i < 64; i += 16) s += As[c * 64 + i] * As[c * 64 + i];
         s = group16_sum(s);
-        if (l8 == 0) sg[c] = sqrt(s);
+        if (l8 == 0) sg[c] = ldexp(sqrt(s), sexp);
     }
     __syncthreads();
     if (tid < q) {
@@ -123,7 +170,7 @@ __global__ void __launch_bounds__(512) svd_jacobi_kernel(const double* A, int ld
     __syncthreads();
     for (int t = tid; t < p * q; t += 512) {
         const int r = t / p, i = t - r * p;
-        G[(size_t)r * p + i] = As[perm[r] * 64 + i];
+        G[(size_t)r * p + i] = ldexp(As[perm[r] * 64 + i], sexp);
     }
     for (int t = tid; t < q * q; t += 512) {
         const int r = t / q, i = t - r * q;
