@@ -11,8 +11,9 @@ accumulation; sketch GEMM, QR, projection, next core and truncation in FP64.
 A step is one whole rounding of X (all hot-path steps), inputs resident in
 HBM.  Prints one JSON line.  Also reported:
   * sketch GB/s and the roofline of the partial-contraction kernel
-    (algorithmic bytes per launch / average launch duration, HIP events
-    around the partial-contraction pass on the library's stream);
+    (algorithmic bytes per launch / average launch duration, from HIP event
+    pairs that the library records on this stream around every launch of
+    that kernel during the timed steps);
   * the CPU oracle on the host cores (a bounded sample of full roundings);
   * parity of the last result against the oracle (relative to ||X||).
 """
@@ -46,6 +47,31 @@ def sketch_bytes(dims, ranks, ell, w_bytes):
     return core + wout
 
 
+PMC_SUMMARY = os.path.join(ROOT, "profiles", "pc_kernel_c2_pmc.txt")
+PC_SOURCE = os.path.join(ROOT, "paper_2511_03598_amd", "csrc", "partial.hip")
+
+
+def pmc_traffic(alg_bytes_per_launch):
+    """HBM bytes per partial-contraction launch from the committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE summary, or None when there is none or the
+    kernel source changed since it was taken (the summary records the
+    source's sha256)."""
+    import hashlib
+    try:
+        text = open(PMC_SUMMARY).read()
+    except OSError:
+        return None
+    vals = {}
+    for line in text.splitlines():
+        if "=" in line and not line.startswith("#"):
+            k, v = line.split("=", 1)
+            vals[k.strip()] = v.strip()
+    src = hashlib.sha256(open(PC_SOURCE, "rb").read()).hexdigest()
+    if vals.get("source_sha256") != src or "hbm_bytes_per_launch" not in vals:
+        return None
+    return float(vals["hbm_bytes_per_launch"])
+
+
 def cpu_baseline(x, budget_s):
     from oracle import krp
     try:
@@ -74,6 +100,9 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-parity", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device-to-device copy three times (the "
+                         "reference kernel that scales rocprofv3 FETCH_SIZE/WRITE_SIZE to bytes)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (the design notes "
@@ -82,6 +111,15 @@ def main():
 
     import numpy as np
     import torch
+
+    if args.copy_calibration:
+        src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")  # 1 GiB
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes": src.numel() * 8, "dispatches": 3}), flush=True)
+        return
 
     import paper_2511_03598_amd as ttr
     import ttgen
@@ -99,7 +137,12 @@ def main():
     for _ in range(args.warmup):
         y, info = step()
     torch.cuda.synchronize()
+    # Timed region: K whole roundings, with the library's HIP-event timers on
+    # (event pairs on this stream around each partial-contraction launch and
+    # around each GEMM, QR and SVD).
+    ttr.kernel_timing(True)
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
     ev0.record(stream)
     for _ in range(args.steps):
@@ -107,30 +150,22 @@ def main():
     ev1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    ttr.kernel_timing(False)
     gpu_ms = ev0.elapsed_time(ev1)
     ms_per_step = gpu_ms / args.steps
     value = args.steps / (gpu_ms / 1e3)
+    kt = {k: ttr.kernel_timing_read(k) for k in ttr.KERNEL_KINDS}
 
-    # Partial-contraction pass alone (same stream, same kernels): average
-    # launch duration of the partial-contraction kernel.
+    # Roofline of the partial-contraction kernel: algorithmic bytes of one
+    # pass / launches per pass, over the average recorded launch duration.
+    npc_launches, pc_ms = kt["partial_contraction"]
     npc = D - 1
-    for _ in range(3):
-        ttr.partial_contractions(dev, SEED, 0, ELL, 2, "f32", stream=stream)
-    torch.cuda.synchronize()
-    reps = max(10, args.steps)
-    # Time the pass through the library's own event hooks when available,
-    # else around the ABI call.
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    for _ in range(reps):
-        ttr.partial_contractions(dev, SEED, 0, ELL, 2, "f32", stream=stream)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    pass_ms = e0.elapsed_time(e1) / reps
+    assert npc_launches == npc * args.steps, (npc_launches, npc, args.steps)
     pc_bytes = sketch_bytes(dims, ranks, ELL, 4)
-    per_launch_s = pass_ms / 1e3 / npc
-    achieved = pc_bytes / npc / per_launch_s / 1e9
-    sketch_gbps = pc_bytes / (pass_ms / 1e3) / 1e9
+    avg_launch_s = pc_ms / 1e3 / npc_launches
+    achieved = pc_bytes / npc / avg_launch_s / 1e9
+    sketch_gbps = pc_bytes / (pc_ms / 1e3 / args.steps) / 1e9
+    traffic = pmc_traffic(pc_bytes / npc)
 
     out = {
         "metric": "TT-roundings/s + sketch GB/s vs plain & TT-SVD at rel err <=1e-6",
@@ -149,9 +184,10 @@ def main():
                    "ell": ELL, "target_rank": TARGET, "seed": SEED},
         "sketch_GBps": sketch_gbps,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBPS, "traffic": None,
-                     "kernel": "partial contraction (pc_kernel<float>)",
-                     "bytes_per_launch": pc_bytes / npc, "avg_launch_us": per_launch_s * 1e6},
+                     "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic,
+                     "kernel": "partial contraction (pc_wide_kernel<float>)",
+                     "bytes_per_launch": pc_bytes / npc, "avg_launch_us": avg_launch_s * 1e6},
+        "kernel_ms_per_step": {k: v[1] / args.steps for k, v in kt.items()},
         "wall_s": wall,
     }
     if not args.no_parity:

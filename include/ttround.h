@@ -169,6 +169,30 @@ tt_status tt_qr(double* a, int64_t m, int64_t b, void* stream);
 tt_status tt_svd_small(const double* a, int64_t p, int64_t q, double* g, double* v, double* sig,
                        double tau, int64_t target, int64_t* t_out, void* stream);
 
+/* ---- Kernel timing (instrumentation) ----------------------------------
+ * When enabled, the library records a pair of HIP events on the launch
+ * stream around the launches of each kind below, in every thread: around
+ * each GEMM, QR and SVD, and around the back-to-back partial-contraction
+ * launches of a pass (counted as one launch per core); reading sums the
+ * elapsed times of the recorded pairs.  Used to put per-launch durations
+ * beside algorithmic byte and flop counts. */
+typedef enum {
+    TT_KERNEL_PARTIAL_CONTRACTION = 0, /* one launch per core and pass (Sec. 3.1)  */
+    TT_KERNEL_GEMM = 1,                /* sketch, projection and core products     */
+    TT_KERNEL_QR = 2,                  /* one thin QR (all of its kernels)         */
+    TT_KERNEL_SVD = 3,                 /* one small SVD (Remark 2 truncation)      */
+    TT_KERNEL_KINDS = 4
+} tt_kernel_kind;
+
+/* enable != 0: clear the counters and start recording; 0: stop recording
+ * (recorded pairs stay readable). */
+tt_status tt_kernel_timing(int32_t enable);
+
+/* Launches recorded for `kind` and their summed duration in milliseconds;
+ * waits for the recorded events to complete.  TT_EINVAL on a bad kind or
+ * NULL outputs. */
+tt_status tt_kernel_timing_read(int32_t kind, int64_t* launches, double* total_ms);
+
 #ifdef __cplusplus
 }
 #endif

@@ -78,6 +78,8 @@ def lib():
             "tt_partial_contractions": [P(_View), u64, i64, i64, i32, ctypes.c_int, P(vp), vp],
             "tt_qr": [vp, i64, i64, vp],
             "tt_svd_small": [vp, i64, i64, vp, vp, vp, dbl, i64, P(i64), vp],
+            "tt_kernel_timing": [i32],
+            "tt_kernel_timing_read": [i32, P(i64), P(dbl)],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -245,3 +247,21 @@ def qr(a, stream=None):
     buf = a.t().contiguous()  # column-major m x b
     _check(lib().tt_qr(ctypes.c_void_p(buf.data_ptr()), int(m), int(b), _stream(stream)))
     return buf.t()
+
+
+KERNEL_KINDS = {"partial_contraction": 0, "gemm": 1, "qr": 2, "svd": 3}
+
+
+def kernel_timing(enable):
+    """Start (clearing the counters) or stop recording HIP events around the
+    library's launches of each kernel kind."""
+    _check(lib().tt_kernel_timing(1 if enable else 0))
+
+
+def kernel_timing_read(kind):
+    """(launches, total milliseconds) recorded for a kind (name or id)."""
+    k = KERNEL_KINDS[kind] if isinstance(kind, str) else int(kind)
+    n = ctypes.c_int64()
+    ms = ctypes.c_double()
+    _check(lib().tt_kernel_timing_read(k, ctypes.byref(n), ctypes.byref(ms)))
+    return int(n.value), float(ms.value)

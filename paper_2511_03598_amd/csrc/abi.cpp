@@ -177,4 +177,16 @@ tt_status tt_svd_small(const double* a, int64_t p, int64_t q, double* g, double*
     });
 }
 
+tt_status tt_kernel_timing(int32_t enable) {
+    return guarded([&] { ttr::timing_enable(enable != 0); });
+}
+
+tt_status tt_kernel_timing_read(int32_t kind, int64_t* launches, double* total_ms) {
+    return guarded([&] {
+        if (!launches || !total_ms) throw ttr::Error(TT_EINVAL, "null output");
+        if (kind < 0 || kind >= TT_KERNEL_KINDS) throw ttr::Error(TT_EINVAL, "unknown kernel kind");
+        ttr::timing_read(kind, launches, total_ms);
+    });
+}
+
 }  // extern "C"

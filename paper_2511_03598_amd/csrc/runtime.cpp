@@ -153,6 +153,7 @@ void gemm(Workspace& ws, hipStream_t s, int M, int N, int K, const double* A, in
     }
     double* partials = nullptr;
     if (splits > 1) partials = ws.part.as<double>((size_t)splits * M * N);
+    TimedScope ts(KT_GEMM, s);
     launch_gemm(g, splits, partials, s);
 }
 
@@ -172,6 +173,7 @@ int read_int(Workspace& ws, hipStream_t s, const int* dev) {
 // (decided on the device) Householder TSQR on the untouched panel.
 void qr(Workspace& ws, hipStream_t s, double* a, int m, int b, int lda, double* r_out = nullptr) {
     const QrPlan p = plan_qr(m, b, lda);
+    TimedScope ts(KT_QR, s);
     int* cnt = ws.qr_counters(p.nodes + 8, s);
     int* flags = cnt + p.nodes + 4;  // route flags, set by the fast path
     double* cw = ws.cqws.as<double>(cq_workspace_doubles(m, b));
@@ -283,6 +285,8 @@ struct Sketch {
         for (int j = t; j <= d; ++j) maxn = std::max(maxn, s.n[j - 1]);
         launch_omega(oa, d - t + 1, maxn, st);
         if (prec != 0) launch_fill_int(maxexp, INT_MIN, d + 2, st);
+        // one event pair around the back-to-back partial-contraction launches
+        TimedScope ts(KT_PC, st, d - t + 1);
         for (int k = d; k >= t; --k) {
             PcArgs a{};
             a.X = cores[k - 1];
@@ -356,8 +360,12 @@ void recompress(Workspace& ws, hipStream_t st, const Shape& s, double** cores, i
             q = m;
         }
         const int tgt = target ? (int)target[k - 1] : 0;
-        launch_svd_jacobi(A, b, b, q, G, Vs, sig, tau, tgt, tdev, st);
-        const int t = read_int(ws, st, tdev);
+        {
+            TimedScope ts(KT_SVD, st);
+            launch_svd_jacobi(A, b, b, q, G, Vs, sig, tau, tgt, tdev, st);
+        }
+        // a target rank is known on the host; the tail rule needs the device
+        const int t = (tau >= 0.0) ? read_int(ws, st, tdev) : std::min(std::max(tgt, 1), q);
         static const bool trace = std::getenv("TTR_TRACE_QR") != nullptr;
         if (trace)
             std::fprintf(stderr, "ttr svd p=%d q=%d kept=%d sweeps=%d\n", b, q, t,
@@ -645,8 +653,109 @@ int64_t svd_small(const double* a, int64_t p, int64_t q, double* g, double* v, d
     if (!a || !g || !v || !sig || q < 1 || q > 64 || p < q) throw Error(-1, "bad SVD request");
     WsLease lease;
     int* tdev = lease->tint.as<int>(16);
-    launch_svd_jacobi(a, (int)p, (int)p, (int)q, g, v, sig, tau, (int)target, tdev, st);
+    {
+        TimedScope ts(KT_SVD, st);
+        launch_svd_jacobi(a, (int)p, (int)p, (int)q, g, v, sig, tau, (int)target, tdev, st);
+    }
     return read_int(*lease.ws, st, tdev);
+}
+
+// ---------------------------------------------------------------------------
+// Kernel timing
+// ---------------------------------------------------------------------------
+namespace {
+struct TimingState {
+    std::mutex mu;
+    bool on = false;
+    struct Rec {
+        hipEvent_t e0, e1;
+        int launches;
+    };
+    std::vector<Rec> pending[KT_KINDS];
+    std::vector<hipEvent_t> free_events;
+    int64_t launches[KT_KINDS] = {0, 0, 0, 0};
+    double ms[KT_KINDS] = {0, 0, 0, 0};
+};
+TimingState& timing() {
+    static TimingState* t = new TimingState();  // kept until process exit
+    return *t;
+}
+// Resolve the recorded pairs of one kind into the totals (caller holds mu).
+void drain(TimingState& t, int kind) {
+    for (auto& pr : t.pending[kind]) {
+        TTR_HIP(hipEventSynchronize(pr.e1));
+        float ms = 0.f;
+        TTR_HIP(hipEventElapsedTime(&ms, pr.e0, pr.e1));
+        t.ms[kind] += ms;
+        t.launches[kind] += pr.launches;
+        t.free_events.push_back(pr.e0);
+        t.free_events.push_back(pr.e1);
+    }
+    t.pending[kind].clear();
+}
+// An event from the pool or a new one; nullptr if creation fails.
+hipEvent_t take_event(TimingState& t) {
+    if (!t.free_events.empty()) {
+        hipEvent_t e = t.free_events.back();
+        t.free_events.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    return e;
+}
+}  // namespace
+
+void timing_enable(bool on) {
+    TimingState& t = timing();
+    std::lock_guard<std::mutex> lk(t.mu);
+    if (on) {
+        for (int k = 0; k < KT_KINDS; ++k) {
+            drain(t, k);
+            t.launches[k] = 0;
+            t.ms[k] = 0.0;
+        }
+    }
+    t.on = on;
+}
+
+void timing_read(int kind, int64_t* launches, double* total_ms) {
+    if (kind < 0 || kind >= KT_KINDS) throw Error(-1, "unknown kernel kind");
+    TimingState& t = timing();
+    std::lock_guard<std::mutex> lk(t.mu);
+    drain(t, kind);
+    *launches = t.launches[kind];
+    *total_ms = t.ms[kind];
+}
+
+TimedScope::TimedScope(int kind, hipStream_t s, int launches)
+    : kind_(kind), s_(s), launches_(launches) {
+    TimingState& t = timing();
+    std::lock_guard<std::mutex> lk(t.mu);
+    if (!t.on) return;
+    e0_ = take_event(t);
+    if (e0_ && hipEventRecord(e0_, s_) != hipSuccess) {
+        (void)hipGetLastError();
+        t.free_events.push_back(e0_);
+        e0_ = nullptr;
+    }
+}
+
+TimedScope::~TimedScope() {
+    if (!e0_) return;
+    TimingState& t = timing();
+    std::lock_guard<std::mutex> lk(t.mu);
+    hipEvent_t e1 = take_event(t);
+    if (!e1 || hipEventRecord(e1, s_) != hipSuccess) {
+        (void)hipGetLastError();
+        t.free_events.push_back(e0_);
+        if (e1) t.free_events.push_back(e1);
+        return;
+    }
+    t.pending[kind_].push_back(TimingState::Rec{e0_, e1, launches_});
 }
 
 }  // namespace ttr

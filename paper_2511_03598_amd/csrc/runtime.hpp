@@ -52,4 +52,27 @@ void qr_inplace(double* a, int64_t m, int64_t b, hipStream_t st);
 int64_t svd_small(const double* a, int64_t p, int64_t q, double* g, double* v, double* sig,
                   double tau, int64_t target, hipStream_t st);
 
+// Kernel timing: HIP event pairs around launches of each kind (see
+// tt_kernel_timing in the C header).
+enum { KT_PC = 0, KT_GEMM = 1, KT_QR = 2, KT_SVD = 3, KT_KINDS = 4 };
+void timing_enable(bool on);
+void timing_read(int kind, int64_t* launches, double* total_ms);
+
+// RAII scope: records a start event on construction and a stop event on
+// destruction when timing is enabled; no-op otherwise.  `launches` is the
+// number of back-to-back launches of the kind that the scope brackets.
+class TimedScope {
+   public:
+    TimedScope(int kind, hipStream_t s, int launches = 1);
+    ~TimedScope();
+    TimedScope(const TimedScope&) = delete;
+    TimedScope& operator=(const TimedScope&) = delete;
+
+   private:
+    int kind_;
+    hipStream_t s_;
+    int launches_;
+    hipEvent_t e0_ = nullptr;
+};
+
 }  // namespace ttr
