@@ -62,8 +62,11 @@ typedef enum {
 
 /* Precision of the right-to-left partial contractions (the KRP sketch,
  * Sec. 3.1) only; the sketch, QR, projection, estimator and recompression
- * steps always run in float64.  Reduced precisions keep a power-of-two
- * exponent per sketch column in int32 so that values stay in range. */
+ * steps always run in float64.  F32: float32 operands, storage and
+ * accumulation.  BF16: cores rounded to bfloat16 in registers, W stored in
+ * bfloat16, products accumulated in float32.  Reduced precisions keep a
+ * power-of-two exponent per sketch column in int32 so that values stay in
+ * range. */
 typedef enum { TT_PREC_F64 = 0, TT_PREC_F32 = 1, TT_PREC_BF16 = 2 } tt_prec;
 
 typedef struct {

@@ -46,8 +46,8 @@ ttr::Shape view_shape(const tt_view* x) {
 ttr::Options make_opts(const tt_opts* o) {
     ttr::Options r;
     if (o) {
-        if (o->prec != TT_PREC_F64 && o->prec != TT_PREC_F32)
-            throw ttr::Error(TT_EUNSUPPORTED, "only F64 and F32 partial contractions are built");
+        if (o->prec != TT_PREC_F64 && o->prec != TT_PREC_F32 && o->prec != TT_PREC_BF16)
+            throw ttr::Error(TT_EINVAL, "unknown precision");
         r.prec = (int)o->prec;
         r.f_init = o->f_init;
         if (o->f_init > 0.0 && !(o->f_init < 1.0))

@@ -20,11 +20,15 @@ struct Tile {
     double a[4], b[4];
 };
 
-// Element (k, n) of B as double (FP32 storage scaled by 2^bexp[n] when the
-// sketch is kept in FP32).
+// Element (k, n) of B as double (FP32 or bfloat16 storage scaled by
+// 2^bexp[n] when the sketch is kept in reduced precision).
 __device__ __forceinline__ double load_b(const GemmArgs& g, size_t off, int n) {
     if (g.Bf) {
         const double v = (double)g.Bf[off];
+        return g.bexp ? ldexp(v, g.bexp[n]) : v;
+    }
+    if (g.Bh) {
+        const double v = (double)__uint_as_float((unsigned)g.Bh[off] << 16);
         return g.bexp ? ldexp(v, g.bexp[n]) : v;
     }
     return g.B[off];

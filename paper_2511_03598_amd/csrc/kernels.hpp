@@ -43,6 +43,10 @@ struct PcArgs {
 };
 void launch_pc_f64(const PcArgs& a, hipStream_t s);
 void launch_pc_f32(const PcArgs& a, hipStream_t s);
+// BF16: W storage is bfloat16 (uint16 bits) with per-column exponents.
+void launch_pc_bf16(const PcArgs& a, hipStream_t s);
+void launch_w_bf16_to_f64(const unsigned short* w, const int* colexp, int64_t ldw, int rows, int c0,
+                          int nc, double* out, int64_t ldo, hipStream_t s);
 void launch_fill_int(int* p, int value, int64_t count, hipStream_t s);
 // Convert reduced-precision W (float + colexp) to float64 (for the ABI).
 void launch_w_to_f64(const float* w, const int* colexp, int64_t ldw, int rows, int c0, int nc,
@@ -50,14 +54,15 @@ void launch_w_to_f64(const float* w, const int* colexp, int64_t ldw, int rows, i
 
 // ---- general float64 MFMA GEMM (gemm.hip) ----------------------------------
 // C(m,n) = alpha * sum_k A(m,k) B(k,n) + beta * C(m,n), with arbitrary
-// element strides.  B may instead be float storage Bf with a per-column
-// power-of-two exponent bexp[n] (true B = Bf * 2^bexp[n]).
+// element strides.  B may instead be float storage Bf or bfloat16 storage
+// Bh with a per-column power-of-two exponent bexp[n] (true B = Bf * 2^bexp[n]).
 struct GemmArgs {
     int M, N, K;
     const double* A;
     int64_t sam, sak;
     const double* B;
-    const float* Bf;
+    const float* Bf;             // FP32 storage (with bexp) instead of B
+    const unsigned short* Bh;    // bfloat16 storage (with bexp) instead of B
     const int* bexp;
     int64_t sbk, sbn;
     double* C;

@@ -482,6 +482,198 @@ bool try_launch_wide(const PcArgs& a, hipStream_t s) {
     return true;
 }
 
+
+// ---------------------------------------------------------------------------
+// BF16 variant: X is rounded to bfloat16 in registers, W_{k+1} is stored in
+// bfloat16 (with the same per-column power-of-two exponents as the FP32
+// path) and the b-contraction runs on v_mfma_f32_16x16x16_bf16 with FP32
+// accumulation; the Omega fold and the reductions stay in FP32 and W_k is
+// rounded to bfloat16 once at the end.  A lane's four consecutive k of a
+// 16-wide chunk are exactly its A operand, so one MFMA covers a chunk; W
+// is staged transposed (column-major in LDS) so the matching B operand is
+// one 8-byte LDS read.  Same workgroup shape as the wide FP32 kernel.
+// ---------------------------------------------------------------------------
+typedef short bf16x4_t __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ unsigned short bf16_rne(float f) {
+    unsigned u = __float_as_uint(f);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (unsigned short)(u >> 16);
+}
+__device__ __forceinline__ float bf16_to_f32(unsigned short h) {
+    return __uint_as_float((unsigned)h << 16);
+}
+
+template <bool KEVEN, int KG, int WSCH>
+__global__ void __launch_bounds__(KG * 256) pc_bf16_kernel(PcArgs p) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int K = p.r1, n = p.n;
+    const int chunks = (K + 15) / 16;
+    const int K16 = 16 * chunks;
+    const int LDK = K16 + 8;  // transposed row stride (bf16 elements)
+    unsigned short* Wt = reinterpret_cast<unsigned short*>(smem_raw);  // 64 x LDK
+    float* red = reinterpret_cast<float*>(Wt + (size_t)64 * LDK);       // [KG*4][64]
+    const int a = blockIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int wg = wv >> 2, wr = wv & 3;
+    const int li = lane & 15, lg = lane >> 4;
+    const int colbase = p.c0 + blockIdx.y * 64;
+    const int ncb = min(64, p.c0 + p.nc - colbase);
+    const unsigned short* Wn = static_cast<const unsigned short*>(p.Wn);
+    const int kbeg = 16 * ((wg * chunks) / KG);
+    const int kend = min(K, 16 * (((wg + 1) * chunks) / KG));
+    const bool has_k = kend > kbeg;
+    const double* Xa = p.X + (size_t)a * n * K;
+
+    float in_scale = 1.f;
+    int in_e = 0;
+    if (p.in_maxexp != nullptr) {
+        const int e = *p.in_maxexp;
+        in_e = (e == INT_MIN) ? 0 : e;
+        in_scale = (float)ldexp(1.0, -in_e);
+    }
+
+    double buf[4 * WSCH];
+    auto load = [&](int rc, int k0) {
+        const double* xr = Xa + (size_t)min(rc + 16 * wr + li, n - 1) * K;
+#pragma unroll
+        for (int c = 0; c < WSCH; ++c) {
+            const int kb = k0 + 16 * c + 4 * lg;
+            if (KEVEN) {
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const double2_t v =
+                        *reinterpret_cast<const double2_t*>(xr + min(kb + 2 * h, kend - 2));
+                    buf[4 * c + 2 * h] = v[0];
+                    buf[4 * c + 2 * h + 1] = v[1];
+                }
+            } else {
+#pragma unroll
+                for (int s2 = 0; s2 < 4; ++s2) buf[4 * c + s2] = xr[min(kb + s2, kend - 1)];
+            }
+        }
+    };
+    // Stage W_{k+1}: thread -> (row k, column c); element loads are 2 bytes,
+    // issued in rounds of SR before the X loads of the first slab.
+    {
+        constexpr int SR = 16;
+        const int nthr = KG * 256, total = K16 * 64;
+        const int c = tid & 63, cc = colbase + min(c, ncb - 1);
+        const bool cok = c < ncb;
+        for (int base = 0; base < total; base += nthr * SR) {
+            unsigned short v[SR];
+#pragma unroll
+            for (int e = 0; e < SR; ++e) {
+                const int k = min((base + e * nthr + tid) >> 6, K - 1);
+                v[e] = Wn ? Wn[(size_t)k * p.ldw + cc] : (unsigned short)(k == 0 ? 0x3F80 : 0);
+            }
+            if (base == 0 && has_k) load(0, kbeg);
+#pragma unroll
+            for (int e = 0; e < SR; ++e) {
+                const int idx = base + e * nthr + tid;
+                const int k = idx >> 6;
+                const float x = (k < K && cok) ? bf16_to_f32(v[e]) * in_scale : 0.f;
+                if (idx < total) Wt[c * LDK + k] = bf16_rne(x);
+            }
+        }
+        if (total == 0 && has_k) load(0, kbeg);
+    }
+    __syncthreads();
+
+    float part[4] = {0.f, 0.f, 0.f, 0.f};
+    for (int rc = 0; rc < n; rc += 64) {
+        float om[4][4];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int i = min(rc + 16 * wr + mfma_row_f32(lg, v), n - 1);
+            const double* orow = p.Om + (size_t)i * p.ldo + colbase;
+#pragma unroll
+            for (int nb = 0; nb < 4; ++nb) om[v][nb] = (float)orow[min(nb * 16 + li, ncb - 1)];
+        }
+        float4_t acc[4];
+#pragma unroll
+        for (int nb = 0; nb < 4; ++nb) acc[nb] = float4_t{0.f, 0.f, 0.f, 0.f};
+        if (has_k) {
+            const bool rok = rc + 16 * wr + li < n;
+            for (int k0 = kbeg; k0 < kend; k0 += 16 * WSCH) {
+#pragma unroll
+                for (int c = 0; c < WSCH; ++c) {
+                    const int kc = k0 + 16 * c;
+                    if (kc < kend) {
+                        bf16x4_t av;
+#pragma unroll
+                        for (int s2 = 0; s2 < 4; ++s2) {
+                            const bool ok = rok && kc + 4 * lg + s2 < kend;
+                            av[s2] = (short)bf16_rne(ok ? (float)buf[4 * c + s2] : 0.f);
+                        }
+#pragma unroll
+                        for (int nb = 0; nb < 4; ++nb) {
+                            const bf16x4_t bv = *reinterpret_cast<const bf16x4_t*>(
+                                Wt + (nb * 16 + li) * LDK + kc + 4 * lg);
+                            acc[nb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc[nb], 0, 0, 0);
+                        }
+                    }
+                }
+                const int nk0 = k0 + 16 * WSCH;
+                if (nk0 < kend)
+                    load(rc, nk0);
+                else if (rc + 64 < n)
+                    load(rc + 64, kbeg);
+            }
+        }
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const bool iok = rc + 16 * wr + mfma_row_f32(lg, v) < n;
+#pragma unroll
+            for (int nb = 0; nb < 4; ++nb) {
+                const float o = (iok && nb * 16 + li < ncb) ? om[v][nb] : 0.f;
+                part[nb] += acc[nb][v] * o;
+            }
+        }
+    }
+#pragma unroll
+    for (int nb = 0; nb < 4; ++nb) {
+        part[nb] += __shfl_xor(part[nb], 16, 64);
+        part[nb] += __shfl_xor(part[nb], 32, 64);
+    }
+    if (lg == 0) {
+#pragma unroll
+        for (int nb = 0; nb < 4; ++nb) red[wv * 64 + nb * 16 + li] = part[nb];
+    }
+    __syncthreads();
+    if (tid < 64) {
+        const int c = tid;
+        float v = 0.f;
+#pragma unroll
+        for (int w = 0; w < KG * 4; ++w) v += red[w * 64 + c];
+        const unsigned short hv = bf16_rne(v);
+        unsigned short* Wo = static_cast<unsigned short*>(p.Wout);
+        if (c < ncb) Wo[(size_t)a * p.ldw + colbase + c] = hv;
+        const float vr = bf16_to_f32(hv);
+        int e = INT_MIN;
+        if (c < ncb && vr != 0.f) {
+            int ex;
+            frexp((double)vr, &ex);
+            e = ex;
+        }
+        e = wave_max_int(e);
+        if (c == 0 && e != INT_MIN) atomicMax(p.out_maxexp, e);
+        if (a == 0 && c < ncb) {
+            const int base = (p.in_colexp != nullptr) ? p.in_colexp[colbase + c] : 0;
+            p.out_colexp[colbase + c] = base + in_e;
+        }
+    }
+}
+
+__global__ void w_bf16_to_f64_kernel(const unsigned short* w, const int* colexp, int64_t ldw,
+                                     int rows, int c0, int nc, double* out, int64_t ldo) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)rows * nc) return;
+    const int r = (int)(t / nc), c = (int)(t - (int64_t)r * nc);
+    out[(size_t)r * ldo + c] =
+        ldexp((double)bf16_to_f32(w[(size_t)r * ldw + c0 + c]), colexp[c0 + c]);
+}
+
 __global__ void fill_int_kernel(int* p, int value, int64_t count) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t < count) p[t] = value;
@@ -529,6 +721,36 @@ void launch_w_to_f64(const float* w, const int* colexp, int64_t ldw, int rows, i
     const int64_t work = (int64_t)rows * nc;
     if (work <= 0) return;
     hipLaunchKernelGGL(w_to_f64_kernel, dim3(ceil_div(work, 256)), dim3(256), 0, s, w, colexp,
+                       ldw, rows, c0, nc, out, ldo);
+    TTR_CHECK_LAUNCH();
+}
+
+void launch_pc_bf16(const PcArgs& a, hipStream_t s) {
+    constexpr int KG = 2;
+    const size_t lds = (size_t)64 * (16 * ceil_div(a.r1, 16) + 8) * 2 + (size_t)KG * 4 * 64 * 4;
+    if (lds > kWideLdsMax) throw Error(-6, "BF16 partial contraction: rank too large for LDS staging");
+    dim3 grid(a.r0, ceil_div(a.nc, 64));
+    if (a.r1 % 2 == 0) {
+        auto kern = pc_bf16_kernel<true, KG, 8>;
+        static const hipError_t attr = hipFuncSetAttribute(
+            (const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kWideLdsMax);
+        (void)attr;
+        hipLaunchKernelGGL(kern, grid, dim3(KG * 256), lds, s, a);
+    } else {
+        auto kern = pc_bf16_kernel<false, KG, 4>;
+        static const hipError_t attr = hipFuncSetAttribute(
+            (const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kWideLdsMax);
+        (void)attr;
+        hipLaunchKernelGGL(kern, grid, dim3(KG * 256), lds, s, a);
+    }
+    TTR_CHECK_LAUNCH();
+}
+
+void launch_w_bf16_to_f64(const unsigned short* w, const int* colexp, int64_t ldw, int rows, int c0,
+                          int nc, double* out, int64_t ldo, hipStream_t s) {
+    const int64_t work = (int64_t)rows * nc;
+    if (work <= 0) return;
+    hipLaunchKernelGGL(w_bf16_to_f64_kernel, dim3(ceil_div(work, 256)), dim3(256), 0, s, w, colexp,
                        ldw, rows, c0, nc, out, ldo);
     TTR_CHECK_LAUNCH();
 }

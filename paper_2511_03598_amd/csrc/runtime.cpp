@@ -126,7 +126,7 @@ struct WsLease {
 void gemm(Workspace& ws, hipStream_t s, int M, int N, int K, const double* A, int64_t sam,
           int64_t sak, const double* B, int64_t sbk, int64_t sbn, double* C, int64_t scm,
           int64_t scn, double alpha = 1.0, double beta = 0.0, const float* Bf = nullptr,
-          const int* bexp = nullptr) {
+          const int* bexp = nullptr, const unsigned short* Bh = nullptr) {
     if (M <= 0 || N <= 0) return;
     GemmArgs g{};
     g.M = M;
@@ -137,6 +137,7 @@ void gemm(Workspace& ws, hipStream_t s, int M, int N, int K, const double* A, in
     g.sak = sak;
     g.B = B;
     g.Bf = Bf;
+    g.Bh = Bh;
     g.bexp = bexp;
     g.sbk = sbk;
     g.sbn = sbn;
@@ -242,7 +243,7 @@ struct Sketch {
             wo += s.r[j - 1] * lcap;
         }
         om = ws.omega.as<double>(o);
-        const size_t esz = (prec == 0) ? sizeof(double) : sizeof(float);
+        const size_t esz = (prec == 0) ? sizeof(double) : (prec == 1 ? sizeof(float) : 2);
         w = ws.w.get(wo * esz);
         if (prec != 0) {
             colexp = ws.colexp.as<int>((size_t)(d + 2) * lcap);
@@ -263,6 +264,7 @@ struct Sketch {
     double* omega(int j) { return om + om_off[j]; }
     double* wd(int k) { return static_cast<double*>(w) + w_off[k]; }
     float* wf(int k) { return static_cast<float*>(w) + w_off[k]; }
+    unsigned short* wh(int k) { return static_cast<unsigned short*>(w) + w_off[k]; }
     const int* cexp(int k) const { return colexp ? colexp + (size_t)k * lcap : nullptr; }
 
     // Generate columns [ncols, ncols+nc) of Omega_t..Omega_d and contract
@@ -303,13 +305,17 @@ struct Sketch {
                 a.Wout = wd(k);
                 launch_pc_f64(a, st);
             } else {
-                a.Wn = (k == d) ? nullptr : (const void*)wf(k + 1);
-                a.Wout = wf(k);
+                const bool h = (prec == 2);
+                a.Wn = (k == d) ? nullptr : (h ? (const void*)wh(k + 1) : (const void*)wf(k + 1));
+                a.Wout = h ? (void*)wh(k) : (void*)wf(k);
                 a.in_maxexp = (k == d) ? nullptr : maxexp + (k + 1);
                 a.out_maxexp = maxexp + k;
                 a.in_colexp = (k == d) ? nullptr : colexp + (size_t)(k + 1) * lcap;
                 a.out_colexp = colexp + (size_t)k * lcap;
-                launch_pc_f32(a, st);
+                if (h)
+                    launch_pc_bf16(a, st);
+                else
+                    launch_pc_f32(a, st);
             }
         }
         ncols += nc;
@@ -321,9 +327,12 @@ struct Sketch {
                      int64_t ld) {
         if (prec == 0)
             gemm(ws, st, rows, nb, K, Z, K, 1, wd(k + 1) + c0, lcap, 1, S, 1, ld);
-        else
+        else if (prec == 1)
             gemm(ws, st, rows, nb, K, Z, K, 1, nullptr, lcap, 1, S, 1, ld, 1.0, 0.0,
                  wf(k + 1) + c0, cexp(k + 1) + c0);
+        else
+            gemm(ws, st, rows, nb, K, Z, K, 1, nullptr, lcap, 1, S, 1, ld, 1.0, 0.0, nullptr,
+                 cexp(k + 1) + c0, wh(k + 1) + c0);
     }
 };
 
@@ -625,7 +634,7 @@ void partial_contractions(const Shape& s, const double* const* cores, uint64_t s
                           int64_t ncols, int t, int prec, double* const* w, hipStream_t st) {
     if (t < 2 || t > s.d) throw Error(-1, "t must be in [2, d]");
     if (ncols < 1 || col0 < 0) throw Error(-1, "bad column range");
-    if (prec < 0 || prec > 1) throw Error(-6, "precision not supported for partial contractions");
+    if (prec < 0 || prec > 2) throw Error(-6, "precision not supported for partial contractions");
     WsLease lease;
     Workspace& ws = *lease.ws;
     Sketch sk(s, cores, seed, prec, ncols, st, ws, col0);
@@ -634,8 +643,11 @@ void partial_contractions(const Shape& s, const double* const* cores, uint64_t s
         const int rows = (int)s.r[k - 1];
         if (prec == 0)
             launch_copy2d(sk.wd(k), ncols, 1, w[k - t], ncols, 1, rows, (int)ncols, 1.0, st);
-        else
+        else if (prec == 1)
             launch_w_to_f64(sk.wf(k), sk.cexp(k), ncols, rows, 0, (int)ncols, w[k - t], ncols, st);
+        else
+            launch_w_bf16_to_f64(sk.wh(k), sk.cexp(k), ncols, rows, 0, (int)ncols, w[k - t], ncols,
+                                 st);
     }
     TTR_HIP(hipStreamSynchronize(st));
 }

@@ -77,9 +77,9 @@ def test_round_entry_points_validate_before_device():
     assert L.tt_round_fixed(None, None, 4, 1, None, ctypes.byref(out)) == -1
     nul, keep2 = _view(2, [4, 4], [1, 3, 1], [1, 0])
     assert L.tt_round_fixed(ctypes.byref(nul), None, 4, 1, None, ctypes.byref(out)) == -1  # null core
-    opts = ttr._Opts(7, 0.0, 0.0, 0, None)
-    assert L.tt_round_fixed(ctypes.byref(v), None, 4, 1, ctypes.byref(opts), ctypes.byref(out)) == -6
-    assert b"F32" in L.tt_last_error()
+    opts = ttr._Opts(7, 0.0, 0.0, 0, None)                       # no such precision
+    assert L.tt_round_fixed(ctypes.byref(v), None, 4, 1, ctypes.byref(opts), ctypes.byref(out)) == -1
+    assert b"precision" in L.tt_last_error()
 
 
 def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):

@@ -162,3 +162,28 @@ def test_svd_small_rank_deficient(lib):
     sig = sig.cpu().numpy()
     assert t == 6
     assert np.all(sig[6:] < 1e-12 * sig[0])
+
+
+@pytest.mark.parametrize("case,tol", [("c1", 2e-2), ("ragged", 2e-2), ("c2", 5e-2)])
+def test_partial_contractions_bf16(lib, case, tol):
+    """BF16 sketch (bfloat16 operands and W storage, FP32 accumulation)
+    against the FP64 oracle on the same Omega: the bound is a few bfloat16
+    units (2^-8) per chained contraction; the measured error is printed."""
+    if case == "c1":
+        x, cols, seed = ttgen.c1(), 12, 42
+    elif case == "ragged":
+        x, cols, seed = ttgen.small_random(11, 4, [5, 70, 3, 9], [7, 37, 6]), 130, 3
+    else:
+        x, cols, seed = ttgen.c2(), 60, 42
+    dims = [c.shape[1] for c in x]
+    d = len(x)
+    om = krp.draw_omegas(seed, dims, range(2, d + 1), 0, cols)
+    ref = krp.partial_contractions_rl(x, om, 2)
+    got = lib_pc(x, seed, 0, cols, 2, "bf16")
+    worst = 0.0
+    for k in range(2, d + 1):
+        g, r = got[k - 2], ref[k]
+        err = np.linalg.norm(g - r, axis=0) / np.maximum(np.linalg.norm(r, axis=0), 1e-300)
+        worst = max(worst, float(np.max(err)))
+    say("bf16 partial contractions", case, "max column rel err", worst)
+    assert worst <= tol

@@ -17,6 +17,27 @@ pytestmark = pytest.mark.gpu
 TOL = {"f64": 1e-10, "f32": 1e-5}
 
 
+def test_fixed_c1_bf16_sketch_exact_recovery(lib):
+    """A bfloat16 sketch still spans the range when ell >= the true rank,
+    so the FP64 projection recovers X to FP64 accuracy."""
+    x = ttgen.c1()
+    yg, ig = _fixed(lib, x, 12, 42, prec="bf16")
+    assert ig["ranks"] == [1, 10, 12, 12, 12, 12, 1]
+    assert tt.rel_err(x, yg) < 1e-12
+    _check_orth(yg, ig)
+
+
+def test_adaptive_c1_bf16_sketch(lib):
+    """Adaptive rounding with a bfloat16 sketch meets the tolerance and
+    reports ranks no larger than the sketch caps."""
+    x = ttgen.c1()
+    y, info = lib.round_adaptive(to_dev(x), 1e-8, 4, 42, prec="bf16")
+    y = to_host(y)
+    say("adaptive C1 bf16 ranks", info["ranks"], "err", tt.rel_err(x, y))
+    assert tt.rel_err(x, y) <= 1.5e-8
+    assert all(r <= 12 for r in info["ranks"])
+
+
 def _fixed(lib, x, ell, seed, target=None, prec="f64"):
     y, info = lib.round_fixed(to_dev(x), ell, seed, target_ranks=target, prec=prec)
     return to_host(y), info
