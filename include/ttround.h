@@ -172,6 +172,93 @@ tt_status tt_qr(double* a, int64_t m, int64_t b, void* stream);
 tt_status tt_svd_small(const double* a, int64_t p, int64_t q, double* g, double* v, double* sig,
                        double tau, int64_t target, int64_t* t_out, void* stream);
 
+/* Device workspace (bytes, an upper estimate) that one rounding of x uses
+ * besides its inputs and outputs: ell_max > 0 for fixed rank with that
+ * sketch size, <= 0 for adaptive (worst case: ranks up to the caps of
+ * tt_out_capacity).  Host only.  TT_EINVAL on a malformed view. */
+tt_status tt_workspace_bytes(const tt_view* x, int64_t ell_max, tt_prec prec, size_t* bytes);
+
+/* Batched adaptive rounding (Sec. 3.3 applied to `count` independent
+ * tensors): xs[i] is rounded to tol[i] with seed seeds[i] into ys[i] (caller
+ * buffers sized by tt_out_capacity), exactly as tt_round_adaptive would
+ * (bitwise the same result).  The roundings run concurrently on a
+ * process-wide pool of worker threads, each with its own HIP stream and
+ * workspace, so their kernels overlap on the device.  opts (may be NULL)
+ * applies to all; opts->stream is synchronized before the work starts and
+ * the call returns when every result is complete.  Returns TT_OK, or the
+ * status of the first failed tensor (its index is in tt_last_error());
+ * the others are still computed. */
+tt_status tt_round_adaptive_batch(const tt_view* xs, int32_t count, const double* tol,
+                                  int64_t ell_block, const uint64_t* seeds, const tt_opts* opts,
+                                  tt_out* ys);
+
+/* ---- Served rounding ---------------------------------------------------
+ * A server owns worker threads (one HIP stream each) on the device current
+ * at creation.  Requests queue in arrival order and start as soon as a
+ * worker is free and their device-memory footprint (tt_workspace_bytes plus
+ * twice the output capacity) fits the budget beside the running requests
+ * and the results not yet released; a request that fits may start before
+ * an earlier one that does not (at most four times per waiting request).
+ * New requests are admitted while others run, and their kernels overlap on
+ * the device.  Each result is bitwise the same as the synchronous call with
+ * the same arguments. */
+typedef struct {
+    size_t mem_budget; /* bytes; 0 = 80% of the device's free memory        */
+    int32_t workers;   /* requests in flight at once; <= 0 = 8 (max 64)      */
+} tt_server_cfg;
+
+typedef struct {
+    int32_t kind;                /* 0 adaptive (tol, ell_block), 1 fixed   */
+    tt_view x;                   /* borrowed until poll reports completion */
+    double tol;                  /* adaptive                               */
+    int64_t ell_block;           /* adaptive, as in tt_round_adaptive      */
+    int64_t ell;                 /* fixed                                  */
+    const int64_t* target_ranks; /* fixed, host [d+1] or NULL; copied     */
+    uint64_t seed;
+    tt_opts opts;                /* prec, f_init, nrmx, recompress; the
+                                    stream field is ignored               */
+} tt_request;
+
+typedef struct {
+    tt_status status;       /* TT_OK or the rounding's error status         */
+    const char* error;      /* message when status != TT_OK, else ""        */
+    int32_t d;
+    const int64_t* ranks;   /* host [d+1]                                   */
+    double* const* cores;   /* host [d] device pointers, library-owned,
+                               exact size r_{k-1} n_k r_k, row-major        */
+    int32_t orth;           /* 1 left-orth, 2 right-orth                    */
+    tt_info info;
+    double submit_s, start_s, done_s; /* host steady-clock times (seconds)  */
+} tt_result;
+
+typedef struct tt_server tt_server;
+
+/* TT_EINVAL on NULL out; TT_EDEVICE if no device is usable. */
+tt_status tt_server_create(const tt_server_cfg* cfg, tt_server** out);
+
+/* Validates the request on the host and queues it; *ticket identifies it.
+ * TT_ECAPACITY if its footprint exceeds the whole budget. */
+tt_status tt_round_submit(tt_server* s, const tt_request* req, uint64_t* ticket);
+
+/* TT_PENDING while queued or running; TT_OK with *out set once done (the
+ * ticket is then consumed); TT_ENOTFOUND for an unknown ticket. */
+tt_status tt_round_poll(tt_server* s, uint64_t ticket, tt_result** out);
+
+/* Like tt_round_poll but blocks until the request is done. */
+tt_status tt_round_wait(tt_server* s, uint64_t ticket, tt_result** out);
+
+/* Copies the result's cores into caller device buffers dst[k] (each at
+ * least ranks[k-1] n_k ranks[k] doubles) on `stream` and waits for the
+ * copies.  TT_EINVAL for a NULL argument or a failed result. */
+tt_status tt_result_copy(const tt_result* r, double* const* dst, void* stream);
+
+/* Returns the result's device buffers to the server's pool.  Every result
+ * must be released before its server is destroyed. */
+void tt_result_release(tt_result* r);
+
+/* Waits for running requests, drops queued ones, frees the pool. */
+void tt_server_destroy(tt_server* s);
+
 /* ---- Kernel timing (instrumentation) ----------------------------------
  * When enabled, the library records a pair of HIP events on the launch
  * stream around the launches of each kind below, in every thread: around

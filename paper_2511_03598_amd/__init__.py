@@ -55,6 +55,24 @@ class _Info(ctypes.Structure):
                 ("iterations", ctypes.c_int32)]
 
 
+class _ServerCfg(ctypes.Structure):
+    _fields_ = [("mem_budget", ctypes.c_size_t), ("workers", ctypes.c_int32)]
+
+
+class _Request(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("x", _View), ("tol", ctypes.c_double),
+                ("ell_block", ctypes.c_int64), ("ell", ctypes.c_int64),
+                ("target_ranks", ctypes.POINTER(ctypes.c_int64)), ("seed", ctypes.c_uint64),
+                ("opts", _Opts)]
+
+
+class _Result(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int), ("error", ctypes.c_char_p), ("d", ctypes.c_int32),
+                ("ranks", ctypes.POINTER(ctypes.c_int64)), ("cores", ctypes.POINTER(ctypes.c_void_p)),
+                ("orth", ctypes.c_int32), ("info", _Info), ("submit_s", ctypes.c_double),
+                ("start_s", ctypes.c_double), ("done_s", ctypes.c_double)]
+
+
 _lib = None
 
 
@@ -79,6 +97,13 @@ def lib():
             "tt_qr": [vp, i64, i64, vp],
             "tt_svd_small": [vp, i64, i64, vp, vp, vp, dbl, i64, P(i64), vp],
             "tt_kernel_timing": [i32],
+            "tt_workspace_bytes": [P(_View), i64, ctypes.c_int, P(ctypes.c_size_t)],
+            "tt_round_adaptive_batch": [P(_View), i32, P(dbl), i64, P(u64), P(_Opts), P(_Out)],
+            "tt_server_create": [P(_ServerCfg), P(vp)],
+            "tt_round_submit": [vp, P(_Request), P(u64)],
+            "tt_round_poll": [vp, u64, P(P(_Result))],
+            "tt_round_wait": [vp, u64, P(P(_Result))],
+            "tt_result_copy": [P(_Result), P(vp), vp],
             "tt_kernel_timing_read": [i32, P(i64), P(dbl)],
         }
         for name, args in sig.items():
@@ -87,6 +112,10 @@ def lib():
             f.restype = ctypes.c_int
         L.tt_last_error.argtypes = []
         L.tt_last_error.restype = ctypes.c_char_p
+        L.tt_result_release.argtypes = [P(_Result)]
+        L.tt_result_release.restype = None
+        L.tt_server_destroy.argtypes = [vp]
+        L.tt_server_destroy.restype = None
         _lib = L
     return _lib
 
@@ -265,3 +294,121 @@ def kernel_timing_read(kind):
     ms = ctypes.c_double()
     _check(lib().tt_kernel_timing_read(k, ctypes.byref(n), ctypes.byref(ms)))
     return int(n.value), float(ms.value)
+
+
+def workspace_bytes(cores, ell_max=0, prec="f64"):
+    """Upper estimate of the device workspace of one rounding (ell_max > 0:
+    fixed rank with that sketch size; <= 0: adaptive)."""
+    h = _ViewHolder(cores)
+    b = ctypes.c_size_t()
+    _check(lib().tt_workspace_bytes(ctypes.byref(h.view), int(ell_max), _PREC[prec], ctypes.byref(b)))
+    return int(b.value)
+
+
+def round_adaptive_batch(tts, tol, ell_block, seeds, f_init=None, nrmx=None, recompress=0,
+                         prec="f64", stream=None):
+    """Adaptive rounding of many TTs (lists of cores) in one call; tol and
+    seeds are scalars or per-tensor lists.  Returns a list of
+    (cores, info) pairs (info has ranks and orth)."""
+    torch = _torch()
+    count = len(tts)
+    tols = [float(tol)] * count if not hasattr(tol, "__len__") else [float(t) for t in tol]
+    sds = [int(seeds)] * count if not hasattr(seeds, "__len__") else [int(x) for x in seeds]
+    holders, outs, bufs, rk_arrays = [], [], [], []
+    for cores in tts:
+        h = _ViewHolder(cores)
+        d = len(cores)
+        caps = out_capacity(cores)
+        b = [torch.empty(max(int(c), 1), dtype=torch.float64, device=cores[0].device) for c in caps]
+        rk = (ctypes.c_int64 * (d + 1))()
+        ptrs = (ctypes.c_void_p * d)(*[x.data_ptr() for x in b])
+        capa = (ctypes.c_int64 * d)(*caps)
+        holders.append((h, ptrs, capa))
+        outs.append(_Out(d, rk, ptrs, capa, 0))
+        bufs.append(b)
+        rk_arrays.append(rk)
+    views = (_View * count)(*[h[0].view for h in holders])
+    out_arr = (_Out * count)(*outs)
+    o = _opts(prec, f_init, nrmx, recompress, stream)
+    _check(lib().tt_round_adaptive_batch(views, count, (ctypes.c_double * count)(*tols),
+                                         int(ell_block), (ctypes.c_uint64 * count)(*sds),
+                                         ctypes.byref(o), out_arr))
+    res = []
+    for i, cores in enumerate(tts):
+        rk = [int(out_arr[i].ranks[k]) for k in range(len(cores) + 1)]
+        dims = holders[i][0].dims
+        ys = [bufs[i][k][: rk[k] * dims[k] * rk[k + 1]].view(rk[k], dims[k], rk[k + 1])
+              for k in range(len(cores))]
+        res.append((ys, {"ranks": rk, "orth": int(out_arr[i].orth)}))
+    return res
+
+
+class Server:
+    """Served rounding: submit requests (device-resident TT cores), poll
+    for results.  Results are copied into torch tensors and the library's
+    buffers released when a poll returns them."""
+
+    def __init__(self, mem_budget=0, workers=8):
+        self._h = ctypes.c_void_p()
+        cfg = _ServerCfg(int(mem_budget), int(workers))
+        _check(lib().tt_server_create(ctypes.byref(cfg), ctypes.byref(self._h)))
+        self._keep = {}
+
+    def submit(self, cores, kind="adaptive", tol=1e-6, ell_block=0, ell=0, target_ranks=None,
+               seed=0, prec="f64", f_init=None, nrmx=None, recompress=0):
+        h = _ViewHolder(cores)
+        d = len(cores)
+        tg = None
+        if target_ranks is not None:
+            tg = (ctypes.c_int64 * (d + 1))(*[int(x) for x in target_ranks])
+        o = _Opts(_PREC[prec], float(f_init or 0.0), float(nrmx or 0.0), int(recompress), None)
+        req = _Request(0 if kind == "adaptive" else 1, h.view, float(tol), int(ell_block), int(ell),
+                       tg, ctypes.c_uint64(seed), o)
+        t = ctypes.c_uint64()
+        _check(lib().tt_round_submit(self._h, ctypes.byref(req), ctypes.byref(t)))
+        self._keep[int(t.value)] = (h, cores, tg)
+        return int(t.value)
+
+    def _collect(self, ticket, fn):
+        torch = _torch()
+        r = ctypes.POINTER(_Result)()
+        st = fn(self._h, ctypes.c_uint64(ticket), ctypes.byref(r))
+        if st == 1:
+            return None
+        _check(st)
+        try:
+            res = r.contents
+            if res.status != 0:
+                raise TTError(res.status, res.error.decode())
+            d = res.d
+            rk = [int(res.ranks[k]) for k in range(d + 1)]
+            h = self._keep[ticket][0]
+            ys = [torch.empty((rk[k], h.dims[k], rk[k + 1]), dtype=torch.float64, device="cuda")
+                  for k in range(d)]
+            dst = (ctypes.c_void_p * d)(*[t.data_ptr() for t in ys])
+            _check(lib().tt_result_copy(r, dst, _stream(None)))
+            info = {"ranks": rk, "orth": int(res.orth), "submit_s": res.submit_s,
+                    "start_s": res.start_s, "done_s": res.done_s, "tau": res.info.tau,
+                    "nrmx": res.info.nrmx}
+            return ys, info
+        finally:
+            lib().tt_result_release(r)
+            self._keep.pop(ticket, None)
+
+    def poll(self, ticket):
+        """(cores, info) when done, None while pending."""
+        return self._collect(ticket, lib().tt_round_poll)
+
+    def wait(self, ticket):
+        return self._collect(ticket, lib().tt_round_wait)
+
+    def close(self):
+        if self._h:
+            lib().tt_server_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -2,9 +2,13 @@
 // validation, status codes and the thread-local error message.  No C++
 // exception crosses this layer.
 #include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
 #include <string>
 
 #include "../../include/ttround.h"
+#include "executor.hpp"
 #include "runtime.hpp"
 
 namespace {
@@ -80,6 +84,70 @@ void store_info(const ttr::RoundInfo& i) {
     g_info.iterations = i.iterations;
 }
 
+
+void fill_info(tt_info& o, const ttr::RoundInfo& i) {
+    o.tau = i.tau;
+    o.nrmx = i.nrmx;
+    o.min_margin = i.min_margin;
+    o.passes = i.passes;
+    o.iterations = i.iterations;
+}
+
+int64_t out_capacity_total(const ttr::Shape& s, std::vector<int64_t>* per_core) {
+    std::vector<int64_t> c = ttr::rank_caps(s);
+    int64_t tot = 0;
+    per_core->assign(s.d, 0);
+    for (int k = 1; k <= s.d; ++k) {
+        (*per_core)[k - 1] = c[k - 1] * s.n[k - 1] * c[k];
+        tot += (*per_core)[k - 1];
+    }
+    return tot;
+}
+
+}  // namespace
+
+struct tt_server {
+    std::unique_ptr<ttr::Executor> ex;
+    std::mutex mu;
+    std::map<uint64_t, std::shared_ptr<ttr::Job>> jobs;
+    uint64_t next = 1;
+};
+
+namespace {
+
+struct ResultImpl {
+    tt_result pub;  // first member: tt_result* <-> ResultImpl*
+    std::shared_ptr<ttr::Job> job;
+    tt_server* server;
+    std::string err;
+};
+
+tt_result* make_result(tt_server* s, const std::shared_ptr<ttr::Job>& j) {
+    ResultImpl* r = new ResultImpl();
+    r->job = j;
+    r->server = s;
+    r->err = j->error;
+    tt_result& p = r->pub;
+    p.status = (tt_status)j->status;
+    p.error = r->err.c_str();
+    p.d = j->shape.d;
+    p.ranks = j->out_ranks.data();
+    p.cores = j->out_cores.data();
+    p.orth = j->orth;
+    fill_info(p.info, j->info);
+    p.submit_s = j->t_submit;
+    p.start_s = j->t_start;
+    p.done_s = j->t_done;
+    return &r->pub;
+}
+
+std::shared_ptr<ttr::Job> job_from_view(const tt_view* x, int prec) {
+    auto j = std::make_shared<ttr::Job>();
+    j->shape = view_shape(x);
+    j->cores.assign(x->cores, x->cores + x->d);
+    (void)prec;
+    return j;
+}
 }  // namespace
 
 extern "C" {
@@ -187,6 +255,202 @@ tt_status tt_kernel_timing_read(int32_t kind, int64_t* launches, double* total_m
         if (kind < 0 || kind >= TT_KERNEL_KINDS) throw ttr::Error(TT_EINVAL, "unknown kernel kind");
         ttr::timing_read(kind, launches, total_ms);
     });
+}
+
+
+tt_status tt_workspace_bytes(const tt_view* x, int64_t ell_max, tt_prec prec, size_t* bytes) {
+    return guarded([&] {
+        if (!bytes) throw ttr::Error(TT_EINVAL, "null bytes");
+        if (!x) throw ttr::Error(TT_EINVAL, "null tt_view");
+        if (prec != TT_PREC_F64 && prec != TT_PREC_F32 && prec != TT_PREC_BF16)
+            throw ttr::Error(TT_EINVAL, "unknown precision");
+        ttr::Shape s = ttr::make_shape(x->d, x->n, x->ranks);
+        *bytes = ttr::workspace_bytes(s, ell_max, (int)prec);
+    });
+}
+
+tt_status tt_round_adaptive_batch(const tt_view* xs, int32_t count, const double* tol,
+                                  int64_t ell_block, const uint64_t* seeds, const tt_opts* opts,
+                                  tt_out* ys) {
+    return guarded([&] {
+        if (count < 0) throw ttr::Error(TT_EINVAL, "count must be >= 0");
+        if (count == 0) return;
+        if (!xs || !tol || !seeds || !ys) throw ttr::Error(TT_EINVAL, "null batch array");
+        ttr::Options o = make_opts(opts);
+        std::vector<std::shared_ptr<ttr::Job>> jobs;
+        jobs.reserve(count);
+        for (int i = 0; i < count; ++i) {
+            if (!(tol[i] > 0.0)) throw ttr::Error(TT_EINVAL, "tol[" + std::to_string(i) + "] must be > 0");
+            auto j = job_from_view(&xs[i], o.prec);
+            ttr::OutCores oc = out_of(&ys[i], j->shape.d);
+            j->kind = ttr::Job::ADAPTIVE;
+            j->tol = tol[i];
+            j->ell_block = ell_block;
+            j->seed = seeds[i];
+            j->opts = o;
+            j->out_cores.assign(oc.cores, oc.cores + j->shape.d);
+            j->out_cap.assign(oc.cap, oc.cap + j->shape.d);
+            j->footprint = ttr::workspace_bytes(j->shape, 0, o.prec);
+            jobs.push_back(j);
+        }
+        TTR_HIP(hipStreamSynchronize(o.stream));
+        ttr::Executor& ex = ttr::default_executor();
+        int submitted = 0;
+        std::string first_err;
+        int first_code = 0;
+        try {
+            for (auto& j : jobs) {
+                ex.submit(j);
+                ++submitted;
+            }
+        } catch (const ttr::Error& e) {
+            first_code = e.code;
+            first_err = e.what();
+        }
+        jobs.resize(submitted);
+        ex.wait_all(jobs);
+        for (int i = 0; i < submitted; ++i) {
+            const auto& j = jobs[i];
+            if (j->status == 0) {
+                for (int k = 0; k <= j->shape.d; ++k) ys[i].ranks[k] = j->out_ranks[k];
+                ys[i].orth = j->orth;
+            } else if (first_code == 0) {
+                first_code = j->status;
+                first_err = "tensor " + std::to_string(i) + ": " + j->error;
+            }
+        }
+        if (!jobs.empty()) store_info(jobs.back()->info);
+        if (first_code != 0) throw ttr::Error(first_code, first_err);
+    });
+}
+
+tt_status tt_server_create(const tt_server_cfg* cfg, tt_server** out) {
+    return guarded([&] {
+        if (!out) throw ttr::Error(TT_EINVAL, "null out");
+        *out = nullptr;
+        int dev = 0;
+        TTR_HIP(hipGetDevice(&dev));
+        size_t budget = cfg ? cfg->mem_budget : 0;
+        if (budget == 0) {
+            size_t free_b = 0, total_b = 0;
+            TTR_HIP(hipMemGetInfo(&free_b, &total_b));
+            budget = free_b / 10 * 8;
+        }
+        const int workers = (cfg && cfg->workers > 0) ? cfg->workers : 8;
+        std::unique_ptr<tt_server> s(new tt_server());
+        s->ex.reset(new ttr::Executor(dev, workers, budget));
+        *out = s.release();
+    });
+}
+
+tt_status tt_round_submit(tt_server* s, const tt_request* req, uint64_t* ticket) {
+    return guarded([&] {
+        if (!s || !req || !ticket) throw ttr::Error(TT_EINVAL, "null argument");
+        ttr::Options o = make_opts(&req->opts);
+        o.stream = nullptr;
+        auto j = job_from_view(&req->x, o.prec);
+        const int d = j->shape.d;
+        if (req->kind == 0) {
+            if (!(req->tol > 0.0)) throw ttr::Error(TT_EINVAL, "tol must be > 0");
+            j->kind = ttr::Job::ADAPTIVE;
+            j->tol = req->tol;
+            j->ell_block = req->ell_block;
+        } else if (req->kind == 1) {
+            if (req->ell < 1) throw ttr::Error(TT_EINVAL, "ell must be >= 1");
+            if (req->ell > 64) throw ttr::Error(TT_EUNSUPPORTED, "fixed-rank sketch size ell > 64 is not supported");
+            j->kind = ttr::Job::FIXED;
+            j->ell = req->ell;
+            if (req->target_ranks) {
+                if (req->target_ranks[0] != 1 || req->target_ranks[d] != 1)
+                    throw ttr::Error(TT_EINVAL, "target_ranks[0] and [d] must be 1");
+                for (int k = 1; k < d; ++k)
+                    if (req->target_ranks[k] < 1) throw ttr::Error(TT_EINVAL, "target ranks must be >= 1");
+                j->target.assign(req->target_ranks, req->target_ranks + d + 1);
+            }
+        } else {
+            throw ttr::Error(TT_EINVAL, "request kind must be 0 (adaptive) or 1 (fixed)");
+        }
+        j->seed = req->seed;
+        j->opts = o;
+        j->owned_output = true;
+        const int64_t cap_total = out_capacity_total(j->shape, &j->out_cap);
+        // workspace + capacity staging + exact result, each pool buffer at
+        // most twice its size (power-of-two classes)
+        j->footprint = ttr::workspace_bytes(j->shape, j->kind == ttr::Job::FIXED ? j->ell : 0, o.prec) +
+                       4 * (size_t)cap_total * 8;
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->ex->submit(j);
+        const uint64_t t = s->next++;
+        s->jobs[t] = j;
+        *ticket = t;
+    });
+}
+
+static tt_status poll_impl(tt_server* s, uint64_t ticket, tt_result** out, bool block) {
+    return guarded([&] {
+        if (!s || !out) throw ttr::Error(TT_EINVAL, "null argument");
+        *out = nullptr;
+        std::shared_ptr<ttr::Job> j;
+        {
+            std::lock_guard<std::mutex> lk(s->mu);
+            auto it = s->jobs.find(ticket);
+            if (it == s->jobs.end()) throw ttr::Error(TT_ENOTFOUND, "unknown ticket");
+            j = it->second;
+        }
+        if (j->state.load() != 2) {
+            if (!block) throw ttr::Error(TT_PENDING, "request not finished");
+            s->ex->wait_all({j});
+        }
+        {
+            std::lock_guard<std::mutex> lk(s->mu);
+            s->jobs.erase(ticket);
+        }
+        *out = make_result(s, j);
+    });
+}
+
+tt_status tt_round_poll(tt_server* s, uint64_t ticket, tt_result** out) {
+    return poll_impl(s, ticket, out, false);
+}
+
+tt_status tt_round_wait(tt_server* s, uint64_t ticket, tt_result** out) {
+    return poll_impl(s, ticket, out, true);
+}
+
+tt_status tt_result_copy(const tt_result* r, double* const* dst, void* stream) {
+    return guarded([&] {
+        if (!r || !dst) throw ttr::Error(TT_EINVAL, "null argument");
+        if (r->status != TT_OK) throw ttr::Error(TT_EINVAL, "result holds an error");
+        const ResultImpl* ri = reinterpret_cast<const ResultImpl*>(r);
+        const auto& j = *ri->job;
+        hipStream_t st = (hipStream_t)stream;
+        for (int k = 0; k < r->d; ++k) {
+            const size_t bytes = (size_t)j.out_ranks[k] * j.shape.n[k] * j.out_ranks[k + 1] * 8;
+            if (bytes == 0) continue;
+            if (!dst[k]) throw ttr::Error(TT_EINVAL, "null destination core");
+            TTR_HIP(hipMemcpyAsync(dst[k], j.out_cores[k], bytes, hipMemcpyDeviceToDevice, st));
+        }
+        TTR_HIP(hipStreamSynchronize(st));
+    });
+}
+
+void tt_result_release(tt_result* r) {
+    if (!r) return;
+    ResultImpl* ri = reinterpret_cast<ResultImpl*>(r);
+    try {
+        ri->server->ex->release_result(*ri->job);
+    } catch (...) {
+    }
+    delete ri;
+}
+
+void tt_server_destroy(tt_server* s) {
+    if (!s) return;
+    try {
+        s->ex.reset();
+    } catch (...) {
+    }
+    delete s;
 }
 
 }  // extern "C"

@@ -434,6 +434,43 @@ std::vector<int64_t> rank_caps(const Shape& s) {
 }
 
 // ---------------------------------------------------------------------------
+// Workspace estimate
+// ---------------------------------------------------------------------------
+size_t workspace_bytes(const Shape& s, int64_t ell_max, int prec) {
+    const int d = s.d;
+    const std::vector<int64_t> cap = rank_caps(s);
+    std::vector<int64_t> l(d + 1, 1);
+    int64_t lcap = 1, rmax = 1;
+    if (ell_max > 0) {
+        for (int k = 1; k < d; ++k) l[k] = std::min<int64_t>({ell_max, l[k - 1] * s.n[k - 1], s.r[k]});
+        lcap = ell_max;
+    } else {
+        l = cap;
+        for (int k = 1; k < d; ++k) lcap = std::max(lcap, cap[k]);
+        lcap = std::max<int64_t>(lcap, (int64_t)std::ceil(0.1 * (double)lcap));
+    }
+    for (int k = 0; k <= d; ++k) rmax = std::max(rmax, s.r[k]);
+    const size_t esz = prec == 0 ? 8 : (prec == 1 ? 4 : 2);
+    size_t b = 0;
+    int64_t maxy = 1, maxrows = 1;
+    for (int k = 1; k <= d; ++k) {
+        maxy = std::max(maxy, l[k - 1] * s.n[k - 1] * s.r[k]);
+        maxrows = std::max(maxrows, l[k - 1] * s.n[k - 1]);
+        if (k >= 2) {
+            b += (size_t)s.n[k - 1] * lcap * 8;       // Omega
+            b += (size_t)s.r[k - 1] * lcap * esz;     // W
+        }
+    }
+    b += (size_t)(d + 2) * lcap * 4;                  // column exponents
+    b += 2 * (size_t)maxy * 8;                        // sweep ping-pong
+    b += (size_t)maxrows * lcap * 8;                  // Q
+    b += (size_t)lcap * rmax * 8 + (size_t)lcap * 64 * 8;  // M, residual block
+    b += 3 * (size_t)maxrows * 64 * 8;                // QR scratch (CholeskyQR + TSQR)
+    b += (size_t)64 * 64 * 64 * 8;                    // split-K GEMM partials
+    return b + b / 8 + ((size_t)16 << 20);
+}
+
+// ---------------------------------------------------------------------------
 // Fixed rank (Sec. 3.2)
 // ---------------------------------------------------------------------------
 void round_fixed(const Shape& s, const double* const* cores, const int64_t* target, int64_t ell,

@@ -39,6 +39,10 @@ Shape make_shape(int d, const int64_t* n, const int64_t* ranks);
 // c_k = min(r_k, n_1 ... n_k) (k = 0..d, c_0 = c_d = 1).
 std::vector<int64_t> rank_caps(const Shape& s);
 
+// Upper estimate of the device workspace one rounding of this shape uses:
+// ell_max > 0 for fixed rank with that sketch size, <= 0 for adaptive.
+size_t workspace_bytes(const Shape& s, int64_t ell_max, int prec);
+
 void round_fixed(const Shape& s, const double* const* cores, const int64_t* target, int64_t ell,
                  uint64_t seed, const Options& o, OutCores& y, RoundInfo& info);
 void round_adaptive(const Shape& s, const double* const* cores, double tol, int64_t ell_block,

@@ -102,3 +102,39 @@ def test_kernel_timing_host_only():
     assert L.tt_kernel_timing(0) == 0
     assert L.tt_kernel_timing_read(7, ctypes.byref(n), ctypes.byref(ms)) == -1
     assert L.tt_kernel_timing_read(0, None, ctypes.byref(ms)) == -1
+
+
+def test_workspace_bytes_host_only():
+    import paper_2511_03598_amd as ttr
+    L = ttr.lib()
+    v, keep = _view(4, [8, 9, 10, 11], [1, 20, 30, 25, 1], [1, 2, 3, 4])
+    b_small, b_big, b_ad = ctypes.c_size_t(), ctypes.c_size_t(), ctypes.c_size_t()
+    assert L.tt_workspace_bytes(ctypes.byref(v), 4, 0, ctypes.byref(b_small)) == 0
+    assert L.tt_workspace_bytes(ctypes.byref(v), 16, 0, ctypes.byref(b_big)) == 0
+    assert L.tt_workspace_bytes(ctypes.byref(v), 0, 0, ctypes.byref(b_ad)) == 0
+    assert 0 < b_small.value < b_big.value <= b_ad.value
+    assert L.tt_workspace_bytes(ctypes.byref(v), 4, 9, ctypes.byref(b_small)) == -1
+    assert L.tt_workspace_bytes(None, 4, 0, ctypes.byref(b_small)) == -1
+
+
+def test_batch_and_server_validate_on_host():
+    import paper_2511_03598_amd as ttr
+    L = ttr.lib()
+    # empty batch is a no-op; malformed arguments fail before any device call
+    assert L.tt_round_adaptive_batch(None, 0, None, 4, None, None, None) == 0
+    v, keep = _view(2, [4, 4], [1, 3, 1], [1, 2])
+    out = ttr._Out(2, (ctypes.c_int64 * 3)(), (ctypes.c_void_p * 2)(1, 2), (ctypes.c_int64 * 2)(100, 100), 0)
+    views = (ttr._View * 1)(v)
+    outs = (ttr._Out * 1)(out)
+    seeds = (ctypes.c_uint64 * 1)(1)
+    assert L.tt_round_adaptive_batch(views, 1, (ctypes.c_double * 1)(0.0), 4, seeds, None, outs) == -1
+    assert L.tt_round_adaptive_batch(views, -1, (ctypes.c_double * 1)(1e-3), 4, seeds, None, outs) == -1
+    assert L.tt_round_adaptive_batch(views, 1, None, 4, seeds, None, outs) == -1
+    t = ctypes.c_uint64()
+    assert L.tt_round_submit(None, None, ctypes.byref(t)) == -1
+    r = ctypes.POINTER(ttr._Result)()
+    assert L.tt_round_poll(None, 1, ctypes.byref(r)) == -1
+    assert L.tt_server_create(None, None) == -1
+    assert L.tt_result_copy(None, None, None) == -1
+    L.tt_result_release(None)
+    L.tt_server_destroy(None)

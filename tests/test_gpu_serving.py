@@ -1,0 +1,112 @@
+"""Batched and served rounding through the C ABI: every result must be
+bitwise the same as the synchronous single-tensor call with the same
+arguments (alone or in the mix), admission must honour the memory budget,
+and the results must match the oracle."""
+import numpy as np
+import pytest
+
+import ttgen
+from oracle import krp, tt
+from tests.gpu_helpers import rel_tensor_diff, say, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+
+def _mix(count=6, seed=300):
+    """Small TTs of uneven d, n and ranks, each a weighted sum of three TTs
+    (true ranks below the formal ones)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for t in range(count):
+        d = int(rng.integers(3, 7))
+        n = int(rng.integers(4, 11))
+        s = int(rng.integers(2, 7))
+        out.append(ttgen.c4_one(seed + t, d, n, s, q=1e-3))
+    return out
+
+
+def _same(a, b):
+    return len(a) == len(b) and all(np.array_equal(x, y) for x, y in zip(a, b))
+
+
+def test_batch_equals_single_calls(lib):
+    xs = _mix()
+    devs = [to_dev(x) for x in xs]
+    res = lib.round_adaptive_batch(devs, 1e-6, 4, [11 + i for i in range(len(xs))])
+    for i, (x, dv) in enumerate(zip(xs, devs)):
+        ys, info = res[i]
+        y1, i1 = lib.round_adaptive(dv, 1e-6, 4, 11 + i)
+        say("batch", i, info["ranks"])
+        assert info["ranks"] == i1["ranks"]
+        assert _same(to_host(ys), to_host(y1))
+        yo, io = krp.round_adaptive(x, 1e-6, 4, 11 + i)
+        assert info["ranks"] == io["ranks"]
+        assert rel_tensor_diff(x, to_host(ys), yo) <= 1e-10
+
+
+def test_server_results_same_alone_and_in_mix(lib):
+    xs = _mix(8, 400)
+    devs = [to_dev(x) for x in xs]
+    srv = lib.Server(workers=4)
+    try:
+        tickets = []
+        for i, dv in enumerate(devs):
+            if i % 3 == 2:
+                tickets.append(srv.submit(dv, kind="fixed", ell=6, seed=5 + i))
+            else:
+                tickets.append(srv.submit(dv, kind="adaptive", tol=1e-6, ell_block=4, seed=5 + i))
+        got = [srv.wait(t) for t in tickets]
+    finally:
+        srv.close()
+    for i, (dv, (ys, info)) in enumerate(zip(devs, got)):
+        if i % 3 == 2:
+            y1, i1 = lib.round_fixed(dv, 6, 5 + i)
+        else:
+            y1, i1 = lib.round_adaptive(dv, 1e-6, 4, 5 + i)
+        assert info["ranks"] == i1["ranks"]
+        assert _same(to_host(ys), to_host(y1)), i
+        assert info["done_s"] >= info["start_s"] >= info["submit_s"]
+
+
+def test_server_budget_serialises_and_rejects(lib):
+    xs = _mix(3, 500)
+    devs = [to_dev(x) for x in xs]
+    need = max(lib.workspace_bytes(dv, 0) for dv in devs)
+    # room for one request at a time (each reserves at least its workspace
+    # estimate, which is dominated by a fixed 16 MiB here): admission must
+    # serialise them
+    srv = lib.Server(mem_budget=need * 3 // 2, workers=4)
+    try:
+        tickets = [srv.submit(dv, tol=1e-6, ell_block=4, seed=1) for dv in devs]
+        got = [srv.wait(t) for t in tickets]
+        starts = sorted((g[1]["start_s"], g[1]["done_s"]) for g in got)
+        for a, b in zip(starts, starts[1:]):
+            assert b[0] >= a[1] - 1e-6  # no overlap under this budget
+    finally:
+        srv.close()
+    tiny = lib.Server(mem_budget=1 << 20, workers=2)
+    try:
+        with pytest.raises(lib.TTError, match="ECAPACITY"):
+            tiny.submit(devs[0], tol=1e-6, ell_block=4, seed=1)
+    finally:
+        tiny.close()
+
+
+def test_server_poll_until_done(lib):
+    x = ttgen.c1()
+    dv = to_dev(x)
+    srv = lib.Server(workers=2)
+    try:
+        t = srv.submit(dv, tol=1e-8, ell_block=4, seed=42)
+        out = None
+        for _ in range(200000):
+            out = srv.poll(t)
+            if out is not None:
+                break
+        assert out is not None
+        ys, info = out
+        assert tt.rel_err(x, to_host(ys)) <= 1.5e-8
+        with pytest.raises(lib.TTError, match="ENOTFOUND"):
+            srv.poll(t)
+    finally:
+        srv.close()
