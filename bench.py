@@ -100,6 +100,13 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-parity", action="store_true")
+    ap.add_argument("--workload", choices=["c2", "c4", "c5"], default="c2",
+                    help="c2 (default): the fixed-rank rounding the metric is quoted on; "
+                         "c4: batched adaptive rounding vs a plain loop; c5: served rounding "
+                         "under Poisson arrivals (p50/p99 latency)")
+    ap.add_argument("--count", type=int, default=256, help="c4: tensors in the batch")
+    ap.add_argument("--requests", type=int, default=120, help="c5: requests per arrival rate")
+    ap.add_argument("--workers", type=int, default=8, help="c4/c5: concurrent roundings")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy three times (the "
                          "reference kernel that scales rocprofv3 FETCH_SIZE/WRITE_SIZE to bytes)")
@@ -112,6 +119,10 @@ def main():
     import numpy as np
     import torch
 
+    if args.workload == "c4":
+        return run_c4(args)
+    if args.workload == "c5":
+        return run_c5(args)
     if args.copy_calibration:
         src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")  # 1 GiB
         dst = torch.empty_like(src)
@@ -199,6 +210,141 @@ def main():
                          "ranks_equal": info["ranks"] == io["ranks"], "tol": 1e-5}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(x, args.cpu_budget)
+    print(json.dumps(out), flush=True)
+
+
+def run_c4(args):
+    """Batched adaptive rounding (tol 1e-6, ell blocks of 16) of `count`
+    independent TTs of uneven d, n and ranks, against the plain loop of
+    single calls on one stream.  Both produce bitwise the same results."""
+    import torch
+
+    import paper_2511_03598_amd as ttr
+    import ttgen
+    from oracle import tt
+
+    t0 = time.perf_counter()
+    xs = ttgen.c4(count=args.count)
+    gen_s = time.perf_counter() - t0
+    devs = [[torch.tensor(c, device="cuda") for c in x] for x in xs]
+    seeds = [42 + t for t in range(len(xs))]
+    tol, blk = 1e-6, 16
+    nbytes = sum(c.numel() * 8 for x in devs for c in x)
+    # warm-up (workspaces, code objects)
+    ttr.round_adaptive_batch(devs[:8], tol, blk, seeds[:8])
+    for i in range(4):
+        ttr.round_adaptive(devs[i], tol, blk, seeds[i])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plain = [ttr.round_adaptive(devs[i], tol, blk, seeds[i]) for i in range(len(devs))]
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    batch = ttr.round_adaptive_batch(devs, tol, blk, seeds)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    same = all(p[1]["ranks"] == b[1]["ranks"] and all(torch.equal(u, v) for u, v in zip(p[0], b[0]))
+               for p, b in zip(plain, batch))
+    sample = list(range(0, len(xs), max(1, len(xs) // 6)))[:6]
+    errs = [tt.rel_err(xs[i], [c.cpu().numpy() for c in batch[i][0]]) for i in sample]
+    out = {
+        "metric": "TT-roundings/s (batched, C4)", "value": len(xs) / t_batch,
+        "unit": "TT-roundings/s", "n_gpus": 1, "higher_is_better": True, "data": "synthetic",
+        "config": {"workload": "C4: %d TTs, d in [4,16], n in [16,128], formal ranks in [8,128], "
+                               "sum of 3 N(0,1) TTs weighted (1, 1e-4, 1e-8), adaptive tol 1e-6, "
+                               "ell blocks of 16, FP64" % len(xs),
+                   "workers": 8, "input_GB": nbytes / 1e9},
+        "plain_loop_value": len(xs) / t_plain, "speedup_vs_plain": t_plain / t_batch,
+        "batch_s": t_batch, "plain_s": t_plain, "bitwise_equal_to_plain": same,
+        "rel_err_sample": {"tensors": sample, "max": max(errs)}, "generate_s": gen_s,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def run_c5(args):
+    """Served rounding: requests are weighted sums of 8 TTs (d=30, n=32,
+    ranks 50: formal ranks 400) mixed with 20% small ones (d=8, n=16, ranks
+    20), rounded adaptively to tol 1e-6 (ell blocks of 20).  The inputs stay
+    on the device (a pool of distinct tensors that requests draw from).
+    First the saturation throughput mu (all requests queued at once), then
+    Poisson arrivals at lambda = (0.25, 0.5, 0.75, 0.9) mu: p50/p99 of
+    completion minus arrival, and the achieved throughput."""
+    import numpy as np
+    import torch
+
+    import paper_2511_03598_amd as ttr
+    import ttgen
+
+    rng = np.random.default_rng(5000)
+    pool_large = [[torch.tensor(c, device="cuda") for c in ttgen.c5_request(2000 + i)] for i in range(3)]
+    pool_small = [[torch.tensor(c, device="cuda") for c in ttgen.c5_request(3000 + i, small=True)]
+                  for i in range(3)]
+    srv = ttr.Server(workers=args.workers)
+
+    def pick(k):
+        small = rng.random() < 0.2
+        pool = pool_small if small else pool_large
+        return pool[k % len(pool)], small
+
+    def submit(x, seed):
+        return srv.submit(x, tol=1e-6, ell_block=20, seed=seed)
+
+    # warm-up and the alone-vs-mix spot check
+    ref = ttr.round_adaptive(pool_large[0], 1e-6, 20, 7)
+    w = srv.wait(submit(pool_large[0], 7))
+    same = w[0][0].shape == ref[0][0].shape and all(torch.equal(a, b) for a, b in zip(w[0], ref[0]))
+    srv.wait(submit(pool_small[0], 8))
+    # saturation
+    nsat = max(16, args.requests // 4)
+    t0 = time.perf_counter()
+    tk = [submit(pick(i)[0], 100 + i) for i in range(nsat)]
+    res = [srv.wait(t) for t in tk]
+    t_sat = time.perf_counter() - t0
+    mu = nsat / t_sat
+    runs = []
+    for frac in (0.25, 0.5, 0.75, 0.9):
+        lam = frac * mu
+        gaps = rng.exponential(1.0 / lam, size=args.requests)
+        pending, lat, nsmall = [], [], 0
+        t0 = time.perf_counter()
+        tnext = t0
+        for i in range(args.requests):
+            tnext += gaps[i]
+            while True:
+                now = time.perf_counter()
+                if now >= tnext:
+                    break
+                # collect finished requests while waiting for the next arrival
+                still = []
+                for (t, ta) in pending:
+                    r = srv.poll(t)
+                    if r is None:
+                        still.append((t, ta))
+                    else:
+                        lat.append(r[1]["done_s"] - r[1]["submit_s"])
+                pending = still
+                time.sleep(min(0.0005, max(0.0, tnext - now)))
+            x, small = pick(i)
+            nsmall += small
+            pending.append((submit(x, 1000 + i), tnext))
+        for (t, ta) in pending:
+            r = srv.wait(t)
+            lat.append(r[1]["done_s"] - r[1]["submit_s"])
+        wall = time.perf_counter() - t0
+        lat = np.sort(np.array(lat))
+        runs.append({"lambda_frac": frac, "lambda_per_s": lam, "requests": args.requests,
+                     "small": nsmall, "p50_ms": float(np.percentile(lat, 50) * 1e3),
+                     "p99_ms": float(np.percentile(lat, 99) * 1e3),
+                     "throughput_per_s": args.requests / wall})
+    srv.close()
+    out = {"metric": "served TT-roundings/s and p50/p99 latency (C5)", "value": mu,
+           "unit": "TT-roundings/s (saturation)", "n_gpus": 1, "higher_is_better": True,
+           "data": "synthetic",
+           "config": {"workload": "C5: 80% sums of 8 TTs (d=30, n=32, ranks 50, coefficients "
+                                  "g_i 10^-i; formal ranks 400), 20% small (d=8, n=16, ranks 20 x 8), "
+                                  "adaptive tol 1e-6, ell blocks of 20, FP64", "workers": args.workers},
+           "saturation": {"requests": nsat, "seconds": t_sat},
+           "poisson": runs, "alone_equals_mix": same}
     print(json.dumps(out), flush=True)
 
 
