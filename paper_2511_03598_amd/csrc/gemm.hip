@@ -4,7 +4,8 @@
 // M_k H(X_{k+1}) and the recompression products.
 //
 // 64x64 output tile per 256-thread workgroup, K staged through LDS in
-// 16-deep double-buffered slabs, each wave owning a 32x32 quadrant
+// 32-deep double-buffered slabs (eight loads per operand and thread in
+// flight per slab), each wave owning a 32x32 quadrant
 // (2x2 MFMA blocks).  Operands are addressed by element strides so one
 // kernel serves every transpose; the global->LDS thread mapping follows the
 // contiguous dimension so loads stay coalesced.  Split-K writes partial
@@ -14,10 +15,11 @@
 namespace ttr {
 namespace {
 
-constexpr int BM = 64, BN = 64, BK = 16, LDP = BM + 4;
+constexpr int BM = 64, BN = 64, BK = 32, LDP = BM + 4;
+constexpr int TE = BM * BK / 256;  // elements per operand and thread per slab
 
 struct Tile {
-    double a[4], b[4];
+    double a[TE], b[TE];
 };
 
 // Element (k, n) of B as double (FP32 or bfloat16 storage scaled by
@@ -41,41 +43,43 @@ __device__ __forceinline__ double load_b(const GemmArgs& g, size_t off, int n) {
 __device__ __forceinline__ void load_tiles(const GemmArgs& g, int m0, int n0, int k0, int kend,
                                            Tile& t) {
     const int tid = threadIdx.x;
-    // A: 64 (m) x 16 (k)
+    // A: 64 (m) x 32 (k)
     if (g.sak == 1) {
-        const int m = tid >> 2, kk = (tid & 3) * 4;
+        // k contiguous: row m, 8 consecutive k
+        const int m = tid >> 2, kk = (tid & 3) * TE;
         const int gm = m0 + m, gmc = min(gm, g.M - 1);
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
+        for (int q = 0; q < TE; ++q) {
             const int gk = k0 + kk + q;
             const double v = g.A[(size_t)gmc * g.sam + min(gk, kend - 1)];
             t.a[q] = (gm < g.M && gk < kend) ? v : 0.0;
         }
     } else {
-        const int kk = tid >> 4, m = (tid & 15) * 4;
+        // m contiguous (or strided): slab row kk, 8 consecutive m
+        const int kk = tid >> 3, m = (tid & 7) * TE;
         const int gk = k0 + kk, gkc = min(gk, kend - 1);
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
+        for (int q = 0; q < TE; ++q) {
             const int gm = m0 + m + q;
             const double v = g.A[(size_t)min(gm, g.M - 1) * g.sam + (size_t)gkc * g.sak];
             t.a[q] = (gm < g.M && gk < kend) ? v : 0.0;
         }
     }
-    // B: 16 (k) x 64 (n)
+    // B: 32 (k) x 64 (n)
     if (g.sbn == 1 || g.sbk != 1) {
-        const int kk = tid >> 4, nn = (tid & 15) * 4;
+        const int kk = tid >> 3, nn = (tid & 7) * TE;
         const int gk = k0 + kk, gkc = min(gk, kend - 1);
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
+        for (int q = 0; q < TE; ++q) {
             const int gn = n0 + nn + q, gnc = min(gn, g.N - 1);
             const double v = load_b(g, (size_t)gkc * g.sbk + (size_t)gnc * g.sbn, gnc);
             t.b[q] = (gk < kend && gn < g.N) ? v : 0.0;
         }
     } else {
-        const int nn = tid >> 2, kk = (tid & 3) * 4;
+        const int nn = tid >> 2, kk = (tid & 3) * TE;
         const int gn = n0 + nn, gnc = min(gn, g.N - 1);
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
+        for (int q = 0; q < TE; ++q) {
             const int gk = k0 + kk + q;
             const double v = load_b(g, (size_t)min(gk, kend - 1) + (size_t)gnc * g.sbn, gnc);
             t.b[q] = (gk < kend && gn < g.N) ? v : 0.0;
@@ -87,22 +91,22 @@ __device__ __forceinline__ void store_tiles(const GemmArgs& g, const Tile& t, do
                                             double (*Bs)[LDP]) {
     const int tid = threadIdx.x;
     if (g.sak == 1) {
-        const int m = tid >> 2, kk = (tid & 3) * 4;
+        const int m = tid >> 2, kk = (tid & 3) * TE;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) As[kk + q][m] = t.a[q];
+        for (int q = 0; q < TE; ++q) As[kk + q][m] = t.a[q];
     } else {
-        const int kk = tid >> 4, m = (tid & 15) * 4;
+        const int kk = tid >> 3, m = (tid & 7) * TE;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) As[kk][m + q] = t.a[q];
+        for (int q = 0; q < TE; ++q) As[kk][m + q] = t.a[q];
     }
     if (g.sbn == 1 || g.sbk != 1) {
-        const int kk = tid >> 4, nn = (tid & 15) * 4;
+        const int kk = tid >> 3, nn = (tid & 7) * TE;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) Bs[kk][nn + q] = t.b[q];
+        for (int q = 0; q < TE; ++q) Bs[kk][nn + q] = t.b[q];
     } else {
-        const int nn = tid >> 2, kk = (tid & 3) * 4;
+        const int nn = tid >> 2, kk = (tid & 3) * TE;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) Bs[kk + q][nn] = t.b[q];
+        for (int q = 0; q < TE; ++q) Bs[kk + q][nn] = t.b[q];
     }
 }
 
@@ -133,7 +137,7 @@ __global__ void __launch_bounds__(256) gemm_kernel(GemmArgs g, int kchunk, doubl
         const bool more = k0 + BK < kend;
         if (more) load_tiles(g, m0, n0, k0 + BK, kend, t);
 #pragma unroll
-        for (int s = 0; s < 4; ++s) {
+        for (int s = 0; s < BK / 4; ++s) {
             const int kk = 4 * s + lg;
             double av[2], bv[2];
 #pragma unroll

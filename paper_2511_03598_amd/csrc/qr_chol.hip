@@ -96,6 +96,8 @@ __device__ __forceinline__ void store_partial(double* gp, const double4_t acc[4]
 }
 
 __global__ void __launch_bounds__(256) cq_gram_kernel(CqDev q) {
+    // route flags of this QR start at zero (read only by later kernels)
+    if (blockIdx.x == 0 && threadIdx.x < 2) q.flags[threadIdx.x] = 0;
     __shared__ double T[TB * LDT];
     int r0, r1;
     block_rows(q, blockIdx.x, r0, r1);
@@ -325,12 +327,14 @@ __global__ void __launch_bounds__(256) cq_apply_kernel(CqDev q, int pass) {
     if (gram) store_partial(q.gpart + (size_t)blockIdx.x * 4096, gacc);
 }
 
-// R of the panel: R = R_last ... R_1 (upper triangular), column-major,
-// multiplied in LDS by one workgroup.
+// R of the panel: R = R_last ... R_1 (upper triangular, identity-padded),
+// written column-major b x b.  One workgroup; each product is a 64x64x64
+// MFMA (f64 16x16x4) from LDS, wave w computing rows 16w .. 16w+15.
 __global__ void __launch_bounds__(256) cq_rout_kernel(CqDev q) {
     if (q.flags[0]) return;
     const int npass = q.flags[1] ? 3 : 2;
     const int b = q.b, tid = threadIdx.x;
+    const int lane = tid & 63, w = tid >> 6, li = lane & 15, lg = lane >> 4;
     __shared__ double A[64 * LDT];
     __shared__ double B[64 * LDT];
     for (int t = tid; t < 64 * 64; t += 256) A[(t >> 6) * LDT + (t & 63)] = q.rfac[t];
@@ -338,23 +342,25 @@ __global__ void __launch_bounds__(256) cq_rout_kernel(CqDev q) {
         for (int t = tid; t < 64 * 64; t += 256)
             B[(t >> 6) * LDT + (t & 63)] = q.rfac[(size_t)p * 4096 + t];
         __syncthreads();
-        double c[16];
+        // C = B A
+        double4_t acc[4];
 #pragma unroll
-        for (int e = 0; e < 16; ++e) {
-            const int t = tid + 256 * e, i = t >> 6, j = t & 63;
-            double s = 0.0;
-            for (int l = i; l <= j; ++l) s += B[i * LDT + l] * A[l * LDT + j];
-            c[e] = s;
+        for (int nb = 0; nb < 4; ++nb) acc[nb] = double4_t{0, 0, 0, 0};
+#pragma unroll 4
+        for (int kk = 0; kk < 64; kk += 4) {
+            const double bv = B[(w * 16 + li) * LDT + kk + lg];
+#pragma unroll
+            for (int nb = 0; nb < 4; ++nb)
+                acc[nb] = mfma_f64_16x16x4(bv, A[(kk + lg) * LDT + nb * 16 + li], acc[nb]);
         }
         __syncthreads();
 #pragma unroll
-        for (int e = 0; e < 16; ++e) {
-            const int t = tid + 256 * e;
-            A[(t >> 6) * LDT + (t & 63)] = c[e];
-        }
+        for (int nb = 0; nb < 4; ++nb)
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+                A[(w * 16 + mfma_row_f64(lg, v)) * LDT + nb * 16 + li] = acc[nb][v];
         __syncthreads();
     }
-    __syncthreads();
     for (int t = tid; t < b * b; t += 256) {
         const int col = t / b, i = t - col * b;
         q.r_out[t] = (i <= col) ? A[i * LDT + col] : 0.0;
@@ -383,7 +389,6 @@ void launch_cq(double* a, int m, int b, int lda, double* r_out, double* ws, int*
     q.rfac = q.rinv + 3 * 4096;
     q.r_out = r_out;
     q.flags = flags;
-    launch_fill_int(flags, 0, 2, s);
     hipLaunchKernelGGL(cq_gram_kernel, dim3(q.P), dim3(256), 0, s, q);
     TTR_CHECK_LAUNCH();
     for (int pass = 1; pass <= 3; ++pass) {

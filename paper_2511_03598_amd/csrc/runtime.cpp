@@ -149,7 +149,8 @@ void gemm(Workspace& ws, hipStream_t s, int M, int N, int K, const double* A, in
     const int tiles = ceil_div(M, 64) * ceil_div(N, 64);
     int splits = 1;
     if (tiles < 128 && K >= 512) {
-        splits = std::min(ceil_div(K, 256), std::max(1, 256 / tiles));
+        // enough workgroups to cover the chip, K slices of >= 128
+        splits = std::min(ceil_div(K, 128), std::max(1, 256 / tiles));
         splits = std::min(splits, 64);
     }
     double* partials = nullptr;
