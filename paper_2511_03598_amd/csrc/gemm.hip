@@ -22,18 +22,46 @@ struct Tile {
     double a[TE], b[TE];
 };
 
-// Element (k, n) of B as double (FP32 or bfloat16 storage scaled by
-// 2^bexp[n] when the sketch is kept in reduced precision).
-__device__ __forceinline__ double load_b(const GemmArgs& g, size_t off, int n) {
+// TE elements of B as double: FP64 storage, or FP32 / bfloat16 storage
+// scaled by 2^bexp[n] when the sketch is kept in reduced precision.  A
+// sliced B is the sum of its slices in slice order, taken in the storage's
+// arithmetic type (FP64, or FP32 for both reduced formats); the loads of
+// one slice are issued together before they are added.
+__device__ __forceinline__ float stored_f32(const float* p, size_t i) { return p[i]; }
+__device__ __forceinline__ float stored_f32(const unsigned short* p, size_t i) {
+    return __uint_as_float((unsigned)p[i] << 16);
+}
+
+template <typename T>
+__device__ __forceinline__ void load_b_reduced(const GemmArgs& g, const T* B, const size_t (&off)[TE],
+                                               const int (&nn)[TE], double (&out)[TE]) {
+    float v[TE];
+#pragma unroll
+    for (int q = 0; q < TE; ++q) v[q] = stored_f32(B, off[q]);
+    for (int s = 1; s < g.bslices; ++s) {
+        const size_t so = (size_t)s * g.bstride;
+#pragma unroll
+        for (int q = 0; q < TE; ++q) v[q] += stored_f32(B, so + off[q]);
+    }
+#pragma unroll
+    for (int q = 0; q < TE; ++q) out[q] = g.bexp ? ldexp((double)v[q], g.bexp[nn[q]]) : (double)v[q];
+}
+
+__device__ __forceinline__ void load_b(const GemmArgs& g, const size_t (&off)[TE],
+                                       const int (&nn)[TE], double (&out)[TE]) {
     if (g.Bf) {
-        const double v = (double)g.Bf[off];
-        return g.bexp ? ldexp(v, g.bexp[n]) : v;
+        load_b_reduced(g, g.Bf, off, nn, out);
+    } else if (g.Bh) {
+        load_b_reduced(g, g.Bh, off, nn, out);
+    } else {
+#pragma unroll
+        for (int q = 0; q < TE; ++q) out[q] = g.B[off[q]];
+        for (int s = 1; s < g.bslices; ++s) {
+            const size_t so = (size_t)s * g.bstride;
+#pragma unroll
+            for (int q = 0; q < TE; ++q) out[q] += g.B[so + off[q]];
+        }
     }
-    if (g.Bh) {
-        const double v = (double)__uint_as_float((unsigned)g.Bh[off] << 16);
-        return g.bexp ? ldexp(v, g.bexp[n]) : v;
-    }
-    return g.B[off];
 }
 
 // Global -> registers for one K slab.  Indices are clamped into the matrix
@@ -66,25 +94,33 @@ __device__ __forceinline__ void load_tiles(const GemmArgs& g, int m0, int n0, in
         }
     }
     // B: 32 (k) x 64 (n)
+    size_t off[TE];
+    int nn[TE];
+    bool ok[TE];
     if (g.sbn == 1 || g.sbk != 1) {
-        const int kk = tid >> 3, nn = (tid & 7) * TE;
+        const int kk = tid >> 3, n1 = (tid & 7) * TE;
         const int gk = k0 + kk, gkc = min(gk, kend - 1);
 #pragma unroll
         for (int q = 0; q < TE; ++q) {
-            const int gn = n0 + nn + q, gnc = min(gn, g.N - 1);
-            const double v = load_b(g, (size_t)gkc * g.sbk + (size_t)gnc * g.sbn, gnc);
-            t.b[q] = (gk < kend && gn < g.N) ? v : 0.0;
+            const int gn = n0 + n1 + q, gnc = min(gn, g.N - 1);
+            off[q] = (size_t)gkc * g.sbk + (size_t)gnc * g.sbn;
+            nn[q] = gnc;
+            ok[q] = gk < kend && gn < g.N;
         }
     } else {
-        const int nn = tid >> 2, kk = (tid & 3) * TE;
-        const int gn = n0 + nn, gnc = min(gn, g.N - 1);
+        const int n1 = tid >> 2, kk = (tid & 3) * TE;
+        const int gn = n0 + n1, gnc = min(gn, g.N - 1);
 #pragma unroll
         for (int q = 0; q < TE; ++q) {
             const int gk = k0 + kk + q;
-            const double v = load_b(g, (size_t)min(gk, kend - 1) + (size_t)gnc * g.sbn, gnc);
-            t.b[q] = (gk < kend && gn < g.N) ? v : 0.0;
+            off[q] = (size_t)min(gk, kend - 1) + (size_t)gnc * g.sbn;
+            nn[q] = gnc;
+            ok[q] = gk < kend && gn < g.N;
         }
     }
+    load_b(g, off, nn, t.b);
+#pragma unroll
+    for (int q = 0; q < TE; ++q) t.b[q] = ok[q] ? t.b[q] : 0.0;
 }
 
 __device__ __forceinline__ void store_tiles(const GemmArgs& g, const Tile& t, double (*As)[LDP],

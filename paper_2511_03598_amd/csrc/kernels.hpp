@@ -23,39 +23,52 @@ void launch_philox(const uint32_t* ctr, const uint32_t* key, uint32_t* out, int6
 
 // ---- KRP partial contraction of one core (partial.hip) --------------------
 // W_k(a, c) = sum_i Omega_k(i, c) sum_b X_k(a, i, b) W_{k+1}(b, c) for
-// storage columns c in [c0, c0+nc).  W storage is row-major with stride ldw.
-// For reduced precision W is float with a per-column int exponent:
-// true W_k(:, c) = stored(:, c) * 2^colexp_k[c].
+// storage columns c in [c0, c0+nc).  W is stored transposed: entry (a, c)
+// of a slice at c * ld + a, ld a multiple of 4 (at least the row count),
+// and split into slices: W_k is stored as pc_slices(r_{k-1}, r_k, prec)
+// partial matrices (ss elements apart) whose sum, in slice order, is W_k.
+// For reduced precision W is float32 or bfloat16 with a per-column int
+// exponent: true W_k(:, c) = sum of slices(:, c) * 2^colexp_k[c].
 struct PcArgs {
     const double* X;     // core k (r0 x n x r1), float64
     int r0, n, r1;
     const void* Wn;      // W_{k+1} storage (nullptr: the last core, W_{d+1} = 1)
+    int64_t in_ld, in_ss;
+    int in_slices;
     const double* Om;    // Omega_k storage, row stride ldo
     int64_t ldo;
-    void* Wout;          // W_k storage
-    int64_t ldw;
+    void* Wout;          // W_k storage (room for pc_slices(r0, r1, prec) slices)
+    int64_t out_ld, out_ss;
     int c0, nc;
     // reduced precision only:
-    const int* in_maxexp;   // max exponent over the pass's block of W_{k+1} (nullptr at k=d)
-    int* out_maxexp;        // atomicMax slot for W_k's block
+    const int* in_maxexp;   // per-workgroup max exponents written by the launch that made
+                            // W_{k+1} in this pass (r1 x ceil(nc/64) x in_slices; nullptr at k=d)
+    int* out_maxexp;        // this launch's entries (r0 x ceil(nc/64) x slices)
     const int* in_colexp;   // colexp_{k+1} (nullptr at k=d)
     int* out_colexp;        // colexp_k
 };
+// Number of K slices of the contraction of an r0 x n x r1 core (prec 0 FP64,
+// 1 FP32, 2 BF16); depends on the shape only, so every column block of W_k
+// is split the same way.
+int pc_slices(int64_t r0, int64_t r1, int prec);
 void launch_pc_f64(const PcArgs& a, hipStream_t s);
 void launch_pc_f32(const PcArgs& a, hipStream_t s);
 // BF16: W storage is bfloat16 (uint16 bits) with per-column exponents.
 void launch_pc_bf16(const PcArgs& a, hipStream_t s);
-void launch_w_bf16_to_f64(const unsigned short* w, const int* colexp, int64_t ldw, int rows, int c0,
-                          int nc, double* out, int64_t ldo, hipStream_t s);
 void launch_fill_int(int* p, int value, int64_t count, hipStream_t s);
-// Convert reduced-precision W (float + colexp) to float64 (for the ABI).
-void launch_w_to_f64(const float* w, const int* colexp, int64_t ldw, int rows, int c0, int nc,
-                     double* out, int64_t ldo, hipStream_t s);
+// out(r, c) = W(r, c0 + c) as float64 for r < rows, c < nc, W transposed
+// with row stride ld: the sum of `slices` slices (sstride elements apart)
+// times 2^colexp[c0 + c] when colexp is given; w is double (prec 0), float
+// (1) or bfloat16 bits (2).
+void launch_w_export(int prec, const void* w, const int* colexp, int64_t ld, int rows, int c0,
+                     int nc, int slices, int64_t sstride, double* out, int64_t ldo, hipStream_t s);
 
 // ---- general float64 MFMA GEMM (gemm.hip) ----------------------------------
 // C(m,n) = alpha * sum_k A(m,k) B(k,n) + beta * C(m,n), with arbitrary
 // element strides.  B may instead be float storage Bf or bfloat16 storage
-// Bh with a per-column power-of-two exponent bexp[n] (true B = Bf * 2^bexp[n]).
+// Bh with a per-column power-of-two exponent bexp[n] (true B = Bf * 2^bexp[n]),
+// and B may be stored as bslices slices bstride elements apart whose sum (in
+// slice order, in the storage's arithmetic type) is B.
 struct GemmArgs {
     int M, N, K;
     const double* A;
@@ -64,6 +77,8 @@ struct GemmArgs {
     const float* Bf;             // FP32 storage (with bexp) instead of B
     const unsigned short* Bh;    // bfloat16 storage (with bexp) instead of B
     const int* bexp;
+    int bslices;                 // <= 1: one slice
+    int64_t bstride;
     int64_t sbk, sbn;
     double* C;
     int64_t scm, scn;

@@ -126,7 +126,8 @@ struct WsLease {
 void gemm(Workspace& ws, hipStream_t s, int M, int N, int K, const double* A, int64_t sam,
           int64_t sak, const double* B, int64_t sbk, int64_t sbn, double* C, int64_t scm,
           int64_t scn, double alpha = 1.0, double beta = 0.0, const float* Bf = nullptr,
-          const int* bexp = nullptr, const unsigned short* Bh = nullptr) {
+          const int* bexp = nullptr, const unsigned short* Bh = nullptr, int bslices = 1,
+          int64_t bstride = 0) {
     if (M <= 0 || N <= 0) return;
     GemmArgs g{};
     g.M = M;
@@ -139,6 +140,8 @@ void gemm(Workspace& ws, hipStream_t s, int M, int N, int K, const double* A, in
     g.Bf = Bf;
     g.Bh = Bh;
     g.bexp = bexp;
+    g.bslices = bslices;
+    g.bstride = bstride;
     g.sbk = sbk;
     g.sbn = sbn;
     g.C = C;
@@ -220,6 +223,10 @@ struct Sketch {
     hipStream_t st;
     Workspace& ws;
     std::vector<int64_t> om_off, w_off;  // by 1-based mode
+    std::vector<int> w_sl;               // slices of W_j
+    std::vector<int64_t> w_ld;           // row stride of W_j (stored transposed: lcap rows)
+    std::vector<int64_t> w_ss;           // elements between slices of W_j
+    std::vector<int64_t> mx_off;         // per-workgroup exponent slots of W_j
     double* om = nullptr;
     void* w = nullptr;
     int* colexp = nullptr;
@@ -236,19 +243,29 @@ struct Sketch {
         const int d = s.d;
         om_off.assign(d + 2, 0);
         w_off.assign(d + 2, 0);
-        int64_t o = 0, wo = 0;
+        w_sl.assign(d + 2, 1);
+        w_ld.assign(d + 2, 4);
+        w_ss.assign(d + 2, 0);
+        mx_off.assign(d + 2, 0);
+        int64_t o = 0, wo = 0, mo = 0;
+        const int64_t gy = (lcap + 63) / 64;
         for (int j = 2; j <= d; ++j) {
             om_off[j] = o;
             o += s.n[j - 1] * lcap;
             w_off[j] = wo;
-            wo += s.r[j - 1] * lcap;
+            w_sl[j] = pc_slices(s.r[j - 1], s.r[j], prec);
+            w_ld[j] = (s.r[j - 1] + 3) / 4 * 4;
+            w_ss[j] = w_ld[j] * lcap;
+            wo += w_sl[j] * w_ss[j];
+            mx_off[j] = mo;
+            mo += s.r[j - 1] * gy * w_sl[j];
         }
         om = ws.omega.as<double>(o);
         const size_t esz = (prec == 0) ? sizeof(double) : (prec == 1 ? sizeof(float) : 2);
         w = ws.w.get(wo * esz);
         if (prec != 0) {
             colexp = ws.colexp.as<int>((size_t)(d + 2) * lcap);
-            maxexp = ws.maxexp.as<int>(d + 2);
+            maxexp = ws.maxexp.as<int>(mo + 64);
         }
         // Per-mode sizes/offsets for modes 2..d (uploaded once per call).
         std::vector<int64_t> hn(d + 1, 0), ho(d + 1, 0);
@@ -287,7 +304,6 @@ struct Sketch {
         int64_t maxn = 1;
         for (int j = t; j <= d; ++j) maxn = std::max(maxn, s.n[j - 1]);
         launch_omega(oa, d - t + 1, maxn, st);
-        if (prec != 0) launch_fill_int(maxexp, INT_MIN, d + 2, st);
         // one event pair around the back-to-back partial-contraction launches
         TimedScope ts(KT_PC, st, d - t + 1);
         for (int k = d; k >= t; --k) {
@@ -298,7 +314,13 @@ struct Sketch {
             a.r1 = (int)s.r[k];
             a.Om = omega(k);
             a.ldo = lcap;
-            a.ldw = lcap;
+            if (k < d) {
+                a.in_ld = w_ld[k + 1];
+                a.in_ss = w_ss[k + 1];
+                a.in_slices = w_sl[k + 1];
+            }
+            a.out_ld = w_ld[k];
+            a.out_ss = w_ss[k];
             a.c0 = (int)ncols;
             a.nc = (int)nc;
             if (prec == 0) {
@@ -309,8 +331,8 @@ struct Sketch {
                 const bool h = (prec == 2);
                 a.Wn = (k == d) ? nullptr : (h ? (const void*)wh(k + 1) : (const void*)wf(k + 1));
                 a.Wout = h ? (void*)wh(k) : (void*)wf(k);
-                a.in_maxexp = (k == d) ? nullptr : maxexp + (k + 1);
-                a.out_maxexp = maxexp + k;
+                a.in_maxexp = (k == d) ? nullptr : maxexp + mx_off[k + 1];
+                a.out_maxexp = maxexp + mx_off[k];
                 a.in_colexp = (k == d) ? nullptr : colexp + (size_t)(k + 1) * lcap;
                 a.out_colexp = colexp + (size_t)k * lcap;
                 if (h)
@@ -323,17 +345,21 @@ struct Sketch {
         ++passes;
     }
 
-    // S(rows x nb) = Z(rows x K) * W_{k+1}(:, c0:c0+nb), S column-major (ld).
+    // S(rows x nb) = Z(rows x K) * W_{k+1}(:, c0:c0+nb), S column-major (ld);
+    // W is stored transposed (entry (b, c) at c * w_ld + b).
     void sketch_gemm(int k, const double* Z, int rows, int K, int64_t c0, int nb, double* S,
                      int64_t ld) {
+        const int sl = w_sl[k + 1];
+        const int64_t ss = w_ss[k + 1], wl = w_ld[k + 1], off = c0 * wl;
         if (prec == 0)
-            gemm(ws, st, rows, nb, K, Z, K, 1, wd(k + 1) + c0, lcap, 1, S, 1, ld);
+            gemm(ws, st, rows, nb, K, Z, K, 1, wd(k + 1) + off, 1, wl, S, 1, ld, 1.0, 0.0, nullptr,
+                 nullptr, nullptr, sl, ss);
         else if (prec == 1)
-            gemm(ws, st, rows, nb, K, Z, K, 1, nullptr, lcap, 1, S, 1, ld, 1.0, 0.0,
-                 wf(k + 1) + c0, cexp(k + 1) + c0);
+            gemm(ws, st, rows, nb, K, Z, K, 1, nullptr, 1, wl, S, 1, ld, 1.0, 0.0,
+                 wf(k + 1) + off, cexp(k + 1) + c0, nullptr, sl, ss);
         else
-            gemm(ws, st, rows, nb, K, Z, K, 1, nullptr, lcap, 1, S, 1, ld, 1.0, 0.0, nullptr,
-                 cexp(k + 1) + c0, wh(k + 1) + c0);
+            gemm(ws, st, rows, nb, K, Z, K, 1, nullptr, 1, wl, S, 1, ld, 1.0, 0.0, nullptr,
+                 cexp(k + 1) + c0, wh(k + 1) + off, sl, ss);
     }
 };
 
@@ -459,7 +485,9 @@ size_t workspace_bytes(const Shape& s, int64_t ell_max, int prec) {
         maxrows = std::max(maxrows, l[k - 1] * s.n[k - 1]);
         if (k >= 2) {
             b += (size_t)s.n[k - 1] * lcap * 8;       // Omega
-            b += (size_t)s.r[k - 1] * lcap * esz;     // W
+            const int64_t sl = pc_slices(s.r[k - 1], s.r[k], prec);
+            b += (size_t)sl * ((s.r[k - 1] + 3) / 4 * 4) * lcap * esz;   // W slices
+            b += (size_t)sl * s.r[k - 1] * ((lcap + 63) / 64) * 4;       // exponent slots
         }
     }
     b += (size_t)(d + 2) * lcap * 4;                  // column exponents
@@ -678,14 +706,10 @@ void partial_contractions(const Shape& s, const double* const* cores, uint64_t s
     Sketch sk(s, cores, seed, prec, ncols, st, ws, col0);
     sk.pass(t, ncols);
     for (int k = t; k <= s.d; ++k) {
-        const int rows = (int)s.r[k - 1];
-        if (prec == 0)
-            launch_copy2d(sk.wd(k), ncols, 1, w[k - t], ncols, 1, rows, (int)ncols, 1.0, st);
-        else if (prec == 1)
-            launch_w_to_f64(sk.wf(k), sk.cexp(k), ncols, rows, 0, (int)ncols, w[k - t], ncols, st);
-        else
-            launch_w_bf16_to_f64(sk.wh(k), sk.cexp(k), ncols, rows, 0, (int)ncols, w[k - t], ncols,
-                                 st);
+        const void* wk = prec == 0 ? (const void*)sk.wd(k)
+                                   : (prec == 1 ? (const void*)sk.wf(k) : (const void*)sk.wh(k));
+        launch_w_export(prec, wk, sk.cexp(k), sk.w_ld[k], (int)s.r[k - 1], 0, (int)ncols, sk.w_sl[k],
+                        sk.w_ss[k], w[k - t], ncols, st);
     }
     TTR_HIP(hipStreamSynchronize(st));
 }
