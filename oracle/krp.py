@@ -31,6 +31,12 @@ design notes of the repository):
   * Oversampling (ell larger than the target ranks) and Remark 2 use a
     right-to-left pass: H(Y_k)^T = QR, SVD of R^T, truncate by tau (tail
     rule) or to the target rank, fold U*S into core k-1.
+  * Sums of TT tensors (the remark on sums): the result is defined as the
+    rounding of the formal sum sum_i w_i X^(i) (first cores side by side with
+    the weights, block-diagonal middle cores, stacked last cores) with the
+    same Gaussian factors.  Sketching the summands separately changes only
+    the order of floating-point operations: the partial contractions of the
+    formal sum are the summands' partial contractions stacked by rows.
 """
 
 import math
@@ -226,3 +232,22 @@ def round_adaptive(cores, tol, ell_block, seed, nrmx=None, f_init=0.1,
         ys = recompress_rl(ys, tau=tau)
     info["ranks"] = [1] + [int(c.shape[2]) for c in ys]
     return ys, info
+
+
+def partial_contractions_sum(tts, omegas, t):
+    """Per-summand partial contractions with shared Omega (the remark on
+    sums): W_k of the formal sum is these stacked by rows, summand order."""
+    ws = [partial_contractions_rl(x, omegas, t) for x in tts]
+    return {k: np.concatenate([w[k] for w in ws], axis=0) for k in ws[0]}
+
+
+def round_sum_fixed(tts, ell, seed, weights=None, target_ranks=None):
+    """Fixed-rank rounding of sum_i w_i X^(i): the rounding of the formal sum."""
+    from .tt import formal_sum
+    return round_fixed(formal_sum(tts, weights), ell, seed, target_ranks)
+
+
+def round_sum_adaptive(tts, tol, ell_block, seed, weights=None, **kw):
+    """Adaptive rounding of sum_i w_i X^(i): the rounding of the formal sum."""
+    from .tt import formal_sum
+    return round_adaptive(formal_sum(tts, weights), tol, ell_block, seed, **kw)

@@ -112,3 +112,29 @@ def test_fixed_nonorthonormal_basis_caught(monkeypatch):
 
     monkeypatch.setattr(krp, "qr_pos", wrong)
     _fails(pins_krp.test_fixed_d2_is_halko_range_finder)
+
+
+def test_sum_contractions_summand_order_caught(monkeypatch):
+    from tests import test_oracle_sum as pins_sum
+    orig = krp.partial_contractions_rl
+
+    def wrong(tts, om, t):
+        ws = [orig(x, om, t) for x in reversed(tts)]
+        return {k: np.concatenate([w[k] for w in ws], axis=0) for k in ws[0]}
+
+    monkeypatch.setattr(krp, "partial_contractions_sum", wrong)
+    _fails(pins_sum.test_sum_partial_contractions_vs_definition, 4)
+
+
+def test_sum_weight_applied_twice_caught(monkeypatch):
+    """Each weight applied on both the first and the last core."""
+    from tests import test_oracle_sum as pins_sum
+    orig = tt.formal_sum
+
+    def wrong(tts, weights=None):
+        if weights is None:
+            return orig(tts)
+        return orig(tts, [w * w for w in weights])
+
+    monkeypatch.setattr(tt, "formal_sum", wrong)
+    _fails(pins_sum.test_sum_fixed_d2_is_range_finder_of_weighted_sum)

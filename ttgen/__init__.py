@@ -82,12 +82,17 @@ def c1(seed=1001, d=6, n=10, r=10):
     return formal_sum([z, z, z], [1.0, 0.5, -0.25])
 
 
-def c2(seed=1002, d=20, n=64, r=50, weights=(1.0, 1e-2, 1e-4, 1e-6)):
+def c2_terms(seed=1002, d=20, n=64, r=50, weights=(1.0, 1e-2, 1e-4, 1e-6)):
+    """The summands and weights of c2 (before forming the sum)."""
     rng = rng_for(seed)
     dims = [n] * d
     rk = clamp_ranks(dims, [1] + [r] * (d - 1) + [1])
     tts = [random_tt(rng, dims, rk) for _ in weights]
-    return formal_sum(tts, list(weights))
+    return tts, list(weights)
+
+
+def c2(seed=1002, d=20, n=64, r=50, weights=(1.0, 1e-2, 1e-4, 1e-6)):
+    return formal_sum(*c2_terms(seed, d, n, r, weights))
 
 
 def c3(seed=1003, d=10, n=256, r=200, noise_r=100, noise_sigma=1e-6, decay=8.0):
@@ -140,7 +145,8 @@ def c4(seed=1004, count=256):
     return [c4_one(seed * 1000 + t, *shp) for t, shp in enumerate(shapes)]
 
 
-def c5_request(seed, small=False, terms=8):
+def c5_terms(seed, small=False, terms=8):
+    """The summands and coefficients of a c5 request."""
     rng = rng_for(seed)
     if small:
         d, n, r = 8, 16, 20
@@ -151,7 +157,24 @@ def c5_request(seed, small=False, terms=8):
     tts = [random_tt(rng, dims, rk) for _ in range(terms)]
     g = rng.standard_normal(terms)
     coef = [float(g[i] * 10.0 ** (-i)) for i in range(terms)]
-    return formal_sum(tts, coef)
+    return tts, coef
+
+
+def c5_request(seed, small=False, terms=8):
+    return formal_sum(*c5_terms(seed, small, terms))
+
+
+def sum_terms(seed, d, n, r, count, weights=None):
+    """count random TTs of ranks r (uniform n) and their weights (default
+    1, 10^-3, 10^-6, ...), for sum-rounding tests."""
+    rng = rng_for(seed)
+    dims = [n] * d if np.isscalar(n) else list(n)
+    rr = [1] + ([r] * (d - 1) if np.isscalar(r) else list(r)) + [1]
+    rk = clamp_ranks(dims, rr)
+    tts = [random_tt(rng, dims, rk) for _ in range(count)]
+    if weights is None:
+        weights = [10.0 ** (-3 * i) for i in range(count)]
+    return tts, list(weights)
 
 
 def sec41(seed=1041, d=10, n=100, r=50, eps=1e-5):
