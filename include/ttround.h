@@ -130,6 +130,27 @@ tt_status tt_round_fixed(const tt_view* x, const int64_t* target_ranks, int64_t 
 tt_status tt_round_adaptive(const tt_view* x, double tol, int64_t ell_block, uint64_t seed,
                             const tt_opts* opts, tt_out* y);
 
+/* ---- Rounding of a sum of TT tensors (the remark on sums, Sec. 3.3) ---- *
+ * Y ~ sum_i w_i X^(i) for `count` >= 1 views of the same order d and mode
+ * sizes (each with its own ranks), weights[count] on the host (NULL: all
+ * 1).  The result is the rounding of the formal sum (first cores side by
+ * side times the weights, block-diagonal middle cores, stacked last cores;
+ * its ranks are the summed ranks) with the same seed, but the formal sum is
+ * never assembled: every term is sketched on its own with the shared
+ * Gaussian factors, so the partial contractions and the products with the
+ * next cores cost sum_i r_i^2 instead of (sum_i r_i)^2.  Output capacities
+ * and ranks are those of the formal sum (tt_sum_out_capacity).  Parameters,
+ * options, guarantees and errors as for tt_round_fixed / tt_round_adaptive;
+ * also TT_EINVAL when the views disagree in d or n. */
+tt_status tt_sum_out_capacity(const tt_view* xs, int32_t count, const int64_t* target_ranks,
+                              int64_t* cap);
+tt_status tt_round_sum_fixed(const tt_view* xs, int32_t count, const double* weights,
+                             const int64_t* target_ranks, int64_t ell, uint64_t seed,
+                             const tt_opts* opts, tt_out* y);
+tt_status tt_round_sum_adaptive(const tt_view* xs, int32_t count, const double* weights,
+                                double tol, int64_t ell_block, uint64_t seed, const tt_opts* opts,
+                                tt_out* y);
+
 /* Diagnostics of the calling thread's last tt_round_* call. */
 tt_status tt_last_info(tt_info* info);
 

@@ -105,6 +105,9 @@ def lib():
             "tt_round_wait": [vp, u64, P(P(_Result))],
             "tt_result_copy": [P(_Result), P(vp), vp],
             "tt_kernel_timing_read": [i32, P(i64), P(dbl)],
+            "tt_sum_out_capacity": [P(_View), i32, P(i64), P(i64)],
+            "tt_round_sum_fixed": [P(_View), i32, P(dbl), P(i64), i64, u64, P(_Opts), P(_Out)],
+            "tt_round_sum_adaptive": [P(_View), i32, P(dbl), dbl, i64, u64, P(_Opts), P(_Out)],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -209,6 +212,68 @@ def round_adaptive(cores, tol, ell_block, seed, nrmx=None, f_init=None, recompre
     o = _opts(prec, f_init, nrmx, recompress, stream)
     return _run(cores, lambda h, out: lib().tt_round_adaptive(
         ctypes.byref(h.view), float(tol), int(ell_block), ctypes.c_uint64(seed),
+        ctypes.byref(o), ctypes.byref(out)))
+
+
+class _SumHolder:
+    """ctypes array of tt_view for a list of TTs (kept alive)."""
+
+    def __init__(self, tts, weights):
+        self.holders = [_ViewHolder(c) for c in tts]
+        self.views = (_View * len(tts))(*[h.view for h in self.holders])
+        self.count = len(tts)
+        self.weights = None if weights is None else (ctypes.c_double * len(tts))(*[float(w) for w in weights])
+        if weights is not None and len(weights) != len(tts):
+            raise ValueError("one weight per term")
+
+
+def sum_out_capacity(tts):
+    h = _SumHolder(tts, None)
+    d = len(tts[0])
+    cap = (ctypes.c_int64 * d)()
+    _check(lib().tt_sum_out_capacity(h.views, h.count, None, cap))
+    return list(cap)
+
+
+def _run_sum(tts, weights, call):
+    torch = _torch()
+    h = _SumHolder(tts, weights)
+    d = len(tts[0])
+    dims = h.holders[0].dims
+    caps = sum_out_capacity(tts)
+    bufs = [torch.empty(max(int(c), 1), dtype=torch.float64, device=tts[0][0].device) for c in caps]
+    ranks = (ctypes.c_int64 * (d + 1))()
+    ptrs = (ctypes.c_void_p * d)(*[b.data_ptr() for b in bufs])
+    capa = (ctypes.c_int64 * d)(*caps)
+    out = _Out(d, ranks, ptrs, capa, 0)
+    _check(call(h, out))
+    rk = list(ranks)
+    res = [bufs[k][: rk[k] * dims[k] * rk[k + 1]].view(rk[k], dims[k], rk[k + 1]) for k in range(d)]
+    return res, {"ranks": rk, "orth": int(out.orth), **last_info()}
+
+
+def round_sum_fixed(tts, ell, seed, weights=None, target_ranks=None, prec="f64", stream=None):
+    """Fixed-rank rounding of sum_i w_i X^(i) (tts: list of core lists), the
+    terms sketched separately.  Returns (cores, info)."""
+    d = len(tts[0])
+    tg = None
+    if target_ranks is not None:
+        if len(target_ranks) != d + 1:
+            raise ValueError("target_ranks needs d+1 entries")
+        tg = (ctypes.c_int64 * (d + 1))(*[int(x) for x in target_ranks])
+    o = _opts(prec, 0.0, 0.0, 0, stream)
+    return _run_sum(tts, weights, lambda h, out: lib().tt_round_sum_fixed(
+        h.views, h.count, h.weights, tg, int(ell), ctypes.c_uint64(seed), ctypes.byref(o),
+        ctypes.byref(out)))
+
+
+def round_sum_adaptive(tts, tol, ell_block, seed, weights=None, nrmx=None, f_init=None, recompress=0,
+                       prec="f64", stream=None):
+    """Adaptive rounding of sum_i w_i X^(i) to relative tolerance tol, the
+    terms sketched separately.  Returns (cores, info)."""
+    o = _opts(prec, f_init, nrmx, recompress, stream)
+    return _run_sum(tts, weights, lambda h, out: lib().tt_round_sum_adaptive(
+        h.views, h.count, h.weights, float(tol), int(ell_block), ctypes.c_uint64(seed),
         ctypes.byref(o), ctypes.byref(out)))
 
 

@@ -1,6 +1,7 @@
 // extern "C" boundary of libttround (declared in include/ttround.h): argument
 // validation, status codes and the thread-local error message.  No C++
 // exception crosses this layer.
+#include <cmath>
 #include <cstring>
 #include <map>
 #include <memory>
@@ -178,6 +179,79 @@ tt_status tt_round_fixed(const tt_view* x, const int64_t* target_ranks, int64_t 
         ttr::OutCores oc = out_of(y, s.d);
         ttr::RoundInfo info;
         ttr::round_fixed(s, x->cores, target_ranks, ell, seed, o, oc, info);
+        y->orth = oc.orth;
+        store_info(info);
+    });
+}
+
+namespace {
+ttr::Summands sum_of(const tt_view* xs, int32_t count, const double* weights) {
+    if (!xs) throw ttr::Error(TT_EINVAL, "null tt_view array");
+    if (count < 1) throw ttr::Error(TT_EINVAL, "count must be >= 1");
+    std::vector<ttr::Shape> sh;
+    std::vector<const double* const*> cores;
+    for (int32_t i = 0; i < count; ++i) {
+        sh.push_back(view_shape(&xs[i]));
+        cores.push_back(xs[i].cores);
+    }
+    if (weights)
+        for (int32_t i = 0; i < count; ++i)
+            if (!std::isfinite(weights[i])) throw ttr::Error(TT_EINVAL, "weights must be finite");
+    return ttr::make_sum(sh, cores, weights);
+}
+}  // namespace
+
+tt_status tt_sum_out_capacity(const tt_view* xs, int32_t count, const int64_t* target_ranks,
+                              int64_t* cap) {
+    (void)target_ranks;
+    return guarded([&] {
+        if (!cap) throw ttr::Error(TT_EINVAL, "null cap");
+        if (!xs) throw ttr::Error(TT_EINVAL, "null tt_view array");
+        if (count < 1) throw ttr::Error(TT_EINVAL, "count must be >= 1");
+        std::vector<ttr::Shape> sh;
+        std::vector<const double* const*> cores;
+        for (int32_t i = 0; i < count; ++i) {
+            sh.push_back(ttr::make_shape(xs[i].d, xs[i].n, xs[i].ranks));
+            cores.push_back(nullptr);
+        }
+        const ttr::Summands x = ttr::make_sum(sh, cores, nullptr);
+        std::vector<int64_t> c = ttr::rank_caps(x.fs);
+        for (int k = 1; k <= x.fs.d; ++k) cap[k - 1] = c[k - 1] * x.fs.n[k - 1] * c[k];
+    });
+}
+
+tt_status tt_round_sum_fixed(const tt_view* xs, int32_t count, const double* weights,
+                             const int64_t* target_ranks, int64_t ell, uint64_t seed,
+                             const tt_opts* opts, tt_out* y) {
+    return guarded([&] {
+        const ttr::Summands x = sum_of(xs, count, weights);
+        ttr::Options o = make_opts(opts);
+        if (ell < 1) throw ttr::Error(TT_EINVAL, "ell must be >= 1");
+        const int d = x.fs.d;
+        if (target_ranks) {
+            if (target_ranks[0] != 1 || target_ranks[d] != 1)
+                throw ttr::Error(TT_EINVAL, "target_ranks[0] and [d] must be 1");
+            for (int k = 1; k < d; ++k)
+                if (target_ranks[k] < 1) throw ttr::Error(TT_EINVAL, "target ranks must be >= 1");
+        }
+        ttr::OutCores oc = out_of(y, d);
+        ttr::RoundInfo info;
+        ttr::round_fixed(x, target_ranks, ell, seed, o, oc, info);
+        y->orth = oc.orth;
+        store_info(info);
+    });
+}
+
+tt_status tt_round_sum_adaptive(const tt_view* xs, int32_t count, const double* weights,
+                                double tol, int64_t ell_block, uint64_t seed, const tt_opts* opts,
+                                tt_out* y) {
+    return guarded([&] {
+        const ttr::Summands x = sum_of(xs, count, weights);
+        ttr::Options o = make_opts(opts);
+        if (!(tol > 0.0)) throw ttr::Error(TT_EINVAL, "tol must be > 0");
+        ttr::OutCores oc = out_of(y, x.fs.d);
+        ttr::RoundInfo info;
+        ttr::round_adaptive(x, tol, ell_block, seed, o, oc, info);
         y->orth = oc.orth;
         store_info(info);
     });

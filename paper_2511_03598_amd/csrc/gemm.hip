@@ -22,6 +22,14 @@ struct Tile {
     double a[TE], b[TE];
 };
 
+// Element offset of C(row, col); with cdiv > 0 the column index splits as
+// (col / cdiv, col % cdiv) with strides (cs_hi, scn).
+__device__ __forceinline__ size_t c_offset(const GemmArgs& g, int row, int col) {
+    if (g.cdiv > 0)
+        return (size_t)row * g.scm + (size_t)(col / g.cdiv) * g.cs_hi + (size_t)(col % g.cdiv) * g.scn;
+    return (size_t)row * g.scm + (size_t)col * g.scn;
+}
+
 // TE elements of B as double: FP64 storage, or FP32 / bfloat16 storage
 // scaled by 2^bexp[n] when the sketch is kept in reduced precision.  A
 // sliced B is the sum of its slices in slice order, taken in the storage's
@@ -202,7 +210,7 @@ __global__ void __launch_bounds__(256) gemm_kernel(GemmArgs g, int kchunk, doubl
                     if (split) {
                         partials[((size_t)blockIdx.z * g.M + row) * g.N + col] = acc[i][j][v];
                     } else {
-                        double* c = g.C + (size_t)row * g.scm + (size_t)col * g.scn;
+                        double* c = g.C + c_offset(g, row, col);
                         double val = g.alpha * acc[i][j][v];
                         if (g.beta != 0.0) val += g.beta * (*c);
                         *c = val;
@@ -221,7 +229,7 @@ __global__ void __launch_bounds__(256) gemm_reduce_kernel(GemmArgs g, int splits
     double s = 0.0;
     for (int z = 0; z < splits; ++z) s += partials[(size_t)z * mn + t];
     const int row = (int)(t / g.N), col = (int)(t - (int64_t)row * g.N);
-    double* c = g.C + (size_t)row * g.scm + (size_t)col * g.scn;
+    double* c = g.C + c_offset(g, row, col);
     double val = g.alpha * s;
     if (g.beta != 0.0) val += g.beta * (*c);
     *c = val;

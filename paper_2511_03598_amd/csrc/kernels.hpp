@@ -82,6 +82,8 @@ struct GemmArgs {
     int64_t sbk, sbn;
     double* C;
     int64_t scm, scn;
+    int cdiv;                    // > 0: column c of C at (c / cdiv) * cs_hi + (c % cdiv) * scn
+    int64_t cs_hi;
     double alpha, beta;
 };
 // `partials` must hold splits*M*N doubles when splits > 1.

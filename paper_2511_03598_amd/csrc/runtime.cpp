@@ -162,6 +162,21 @@ void gemm(Workspace& ws, hipStream_t s, int M, int N, int K, const double* A, in
     launch_gemm(g, splits, partials, s);
 }
 
+// The same launch policy for a fully specified GemmArgs.
+void gemm_args(Workspace& ws, hipStream_t s, const GemmArgs& g) {
+    if (g.M <= 0 || g.N <= 0) return;
+    const int tiles = ceil_div(g.M, 64) * ceil_div(g.N, 64);
+    int splits = 1;
+    if (tiles < 128 && g.K >= 512) {
+        splits = std::min(ceil_div(g.K, 128), std::max(1, 256 / tiles));
+        splits = std::min(splits, 64);
+    }
+    double* partials = nullptr;
+    if (splits > 1) partials = ws.part.as<double>((size_t)splits * g.M * g.N);
+    TimedScope ts(KT_GEMM, s);
+    launch_gemm(g, splits, partials, s);
+}
+
 double read_scalar(Workspace& ws, hipStream_t s, const double* dev) {
     TTR_HIP(hipMemcpyAsync(ws.host, dev, sizeof(double), hipMemcpyDeviceToHost, s));
     TTR_HIP(hipStreamSynchronize(s));
@@ -212,21 +227,25 @@ int64_t prod_capped(const std::vector<int64_t>& n, int upto, int64_t cap) {
 }
 
 // ---------------------------------------------------------------------------
-// Partial contractions state (Omega and W for modes 2..d)
+// Partial contractions state (Omega and W for modes 2..d).  For a sum of
+// TTs every term has its own W_j (the formal sum's W_j is the terms' W_j
+// stacked by rows) and all terms share Omega.
 // ---------------------------------------------------------------------------
 struct Sketch {
-    const Shape& s;
-    const double* const* cores;
+    const Summands& x;
     uint64_t seed;
     int prec;
     int64_t lcap;  // column capacity (storage stride)
     hipStream_t st;
     Workspace& ws;
-    std::vector<int64_t> om_off, w_off;  // by 1-based mode
-    std::vector<int> w_sl;               // slices of W_j
-    std::vector<int64_t> w_ld;           // row stride of W_j (stored transposed: lcap rows)
-    std::vector<int64_t> w_ss;           // elements between slices of W_j
-    std::vector<int64_t> mx_off;         // per-workgroup exponent slots of W_j
+    std::vector<int64_t> om_off;  // by 1-based mode
+    struct TermW {
+        std::vector<int64_t> off, ld, ss, mx;  // by 1-based mode j: storage offset, row
+                                               // stride (transposed), slice stride, exponent slots
+        std::vector<int> sl;                   // slices of W_j
+        int64_t cexp_off = 0;
+    };
+    std::vector<TermW> tw;
     double* om = nullptr;
     void* w = nullptr;
     int* colexp = nullptr;
@@ -237,34 +256,45 @@ struct Sketch {
     int64_t gcol0 = 0;
     int passes = 0;
 
-    Sketch(const Shape& sh, const double* const* c, uint64_t sd, int pr, int64_t cap,
-           hipStream_t stream, Workspace& w_, int64_t global_col0 = 0)
-        : s(sh), cores(c), seed(sd), prec(pr), lcap(cap), st(stream), ws(w_), gcol0(global_col0) {
+    Sketch(const Summands& xs, uint64_t sd, int pr, int64_t cap, hipStream_t stream, Workspace& w_,
+           int64_t global_col0 = 0)
+        : x(xs), seed(sd), prec(pr), lcap(cap), st(stream), ws(w_), gcol0(global_col0) {
+        const Shape& s = x.fs;
         const int d = s.d;
         om_off.assign(d + 2, 0);
-        w_off.assign(d + 2, 0);
-        w_sl.assign(d + 2, 1);
-        w_ld.assign(d + 2, 4);
-        w_ss.assign(d + 2, 0);
-        mx_off.assign(d + 2, 0);
-        int64_t o = 0, wo = 0, mo = 0;
-        const int64_t gy = (lcap + 63) / 64;
+        int64_t o = 0;
         for (int j = 2; j <= d; ++j) {
             om_off[j] = o;
             o += s.n[j - 1] * lcap;
-            w_off[j] = wo;
-            w_sl[j] = pc_slices(s.r[j - 1], s.r[j], prec);
-            w_ld[j] = (s.r[j - 1] + 3) / 4 * 4;
-            w_ss[j] = w_ld[j] * lcap;
-            wo += w_sl[j] * w_ss[j];
-            mx_off[j] = mo;
-            mo += s.r[j - 1] * gy * w_sl[j];
+        }
+        const int64_t gy = (lcap + 63) / 64;
+        int64_t wo = 0, mo = 0, co = 0;
+        tw.resize(x.m());
+        for (int i = 0; i < x.m(); ++i) {
+            const Shape& si = x.sh[i];
+            TermW& t = tw[i];
+            t.off.assign(d + 2, 0);
+            t.ld.assign(d + 2, 4);
+            t.ss.assign(d + 2, 0);
+            t.mx.assign(d + 2, 0);
+            t.sl.assign(d + 2, 1);
+            for (int j = 2; j <= d; ++j) {
+                t.off[j] = wo;
+                t.sl[j] = pc_slices(si.r[j - 1], si.r[j], prec);
+                t.ld[j] = (si.r[j - 1] + 3) / 4 * 4;
+                t.ss[j] = t.ld[j] * lcap;
+                wo += t.sl[j] * t.ss[j];
+                t.mx[j] = mo;
+                mo += si.r[j - 1] * gy * t.sl[j];
+            }
+            t.cexp_off = co;
+            co += (int64_t)(d + 2) * lcap;
         }
         om = ws.omega.as<double>(o);
         const size_t esz = (prec == 0) ? sizeof(double) : (prec == 1 ? sizeof(float) : 2);
         w = ws.w.get(wo * esz);
         if (prec != 0) {
-            colexp = ws.colexp.as<int>((size_t)(d + 2) * lcap);
+            colexp = ws.colexp.as<int>(co);
             maxexp = ws.maxexp.as<int>(mo + 64);
         }
         // Per-mode sizes/offsets for modes 2..d (uploaded once per call).
@@ -280,14 +310,18 @@ struct Sketch {
     }
 
     double* omega(int j) { return om + om_off[j]; }
-    double* wd(int k) { return static_cast<double*>(w) + w_off[k]; }
-    float* wf(int k) { return static_cast<float*>(w) + w_off[k]; }
-    unsigned short* wh(int k) { return static_cast<unsigned short*>(w) + w_off[k]; }
-    const int* cexp(int k) const { return colexp ? colexp + (size_t)k * lcap : nullptr; }
+    void* wk(int i, int k) {
+        const size_t esz = (prec == 0) ? sizeof(double) : (prec == 1 ? sizeof(float) : 2);
+        return static_cast<char*>(w) + (size_t)tw[i].off[k] * esz;
+    }
+    const int* cexp(int i, int k) const {
+        return colexp ? colexp + tw[i].cexp_off + (size_t)k * lcap : nullptr;
+    }
 
     // Generate columns [ncols, ncols+nc) of Omega_t..Omega_d and contract
-    // cores t..d (one right-to-left pass).
+    // cores t..d of every term (one right-to-left pass).
     void pass(int t, int64_t nc) {
+        const Shape& s = x.fs;
         const int d = s.d;
         if (nc <= 0) return;
         if (ncols + nc > lcap) throw Error(-6, "sketch column capacity exceeded");
@@ -305,63 +339,145 @@ struct Sketch {
         for (int j = t; j <= d; ++j) maxn = std::max(maxn, s.n[j - 1]);
         launch_omega(oa, d - t + 1, maxn, st);
         // one event pair around the back-to-back partial-contraction launches
-        TimedScope ts(KT_PC, st, d - t + 1);
-        for (int k = d; k >= t; --k) {
-            PcArgs a{};
-            a.X = cores[k - 1];
-            a.r0 = (int)s.r[k - 1];
-            a.n = (int)s.n[k - 1];
-            a.r1 = (int)s.r[k];
-            a.Om = omega(k);
-            a.ldo = lcap;
-            if (k < d) {
-                a.in_ld = w_ld[k + 1];
-                a.in_ss = w_ss[k + 1];
-                a.in_slices = w_sl[k + 1];
-            }
-            a.out_ld = w_ld[k];
-            a.out_ss = w_ss[k];
-            a.c0 = (int)ncols;
-            a.nc = (int)nc;
-            if (prec == 0) {
-                a.Wn = (k == d) ? nullptr : (const void*)wd(k + 1);
-                a.Wout = wd(k);
-                launch_pc_f64(a, st);
-            } else {
-                const bool h = (prec == 2);
-                a.Wn = (k == d) ? nullptr : (h ? (const void*)wh(k + 1) : (const void*)wf(k + 1));
-                a.Wout = h ? (void*)wh(k) : (void*)wf(k);
-                a.in_maxexp = (k == d) ? nullptr : maxexp + mx_off[k + 1];
-                a.out_maxexp = maxexp + mx_off[k];
-                a.in_colexp = (k == d) ? nullptr : colexp + (size_t)(k + 1) * lcap;
-                a.out_colexp = colexp + (size_t)k * lcap;
-                if (h)
-                    launch_pc_bf16(a, st);
-                else
-                    launch_pc_f32(a, st);
+        TimedScope ts(KT_PC, st, (d - t + 1) * x.m());
+        for (int i = 0; i < x.m(); ++i) {
+            const Shape& si = x.sh[i];
+            const TermW& tm = tw[i];
+            for (int k = d; k >= t; --k) {
+                PcArgs a{};
+                a.X = x.cores[i][k - 1];
+                a.r0 = (int)si.r[k - 1];
+                a.n = (int)si.n[k - 1];
+                a.r1 = (int)si.r[k];
+                a.Om = omega(k);
+                a.ldo = lcap;
+                if (k < d) {
+                    a.Wn = wk(i, k + 1);
+                    a.in_ld = tm.ld[k + 1];
+                    a.in_ss = tm.ss[k + 1];
+                    a.in_slices = tm.sl[k + 1];
+                }
+                a.Wout = wk(i, k);
+                a.out_ld = tm.ld[k];
+                a.out_ss = tm.ss[k];
+                a.c0 = (int)ncols;
+                a.nc = (int)nc;
+                if (prec == 0) {
+                    launch_pc_f64(a, st);
+                } else {
+                    a.in_maxexp = (k == d) ? nullptr : maxexp + tm.mx[k + 1];
+                    a.out_maxexp = maxexp + tm.mx[k];
+                    a.in_colexp = (k == d) ? nullptr : cexp(i, k + 1);
+                    a.out_colexp = const_cast<int*>(cexp(i, k));
+                    if (prec == 2)
+                        launch_pc_bf16(a, st);
+                    else
+                        launch_pc_f32(a, st);
+                }
             }
         }
         ncols += nc;
         ++passes;
     }
 
-    // S(rows x nb) = Z(rows x K) * W_{k+1}(:, c0:c0+nb), S column-major (ld);
-    // W is stored transposed (entry (b, c) at c * w_ld + b).
-    void sketch_gemm(int k, const double* Z, int rows, int K, int64_t c0, int nb, double* S,
-                     int64_t ld) {
-        const int sl = w_sl[k + 1];
-        const int64_t ss = w_ss[k + 1], wl = w_ld[k + 1], off = c0 * wl;
-        if (prec == 0)
-            gemm(ws, st, rows, nb, K, Z, K, 1, wd(k + 1) + off, 1, wl, S, 1, ld, 1.0, 0.0, nullptr,
-                 nullptr, nullptr, sl, ss);
-        else if (prec == 1)
-            gemm(ws, st, rows, nb, K, Z, K, 1, nullptr, 1, wl, S, 1, ld, 1.0, 0.0,
-                 wf(k + 1) + off, cexp(k + 1) + c0, nullptr, sl, ss);
-        else
-            gemm(ws, st, rows, nb, K, Z, K, 1, nullptr, 1, wl, S, 1, ld, 1.0, 0.0, nullptr,
-                 cexp(k + 1) + c0, wh(k + 1) + off, sl, ss);
+    // Z = V(Y_k) of the formal sum by column blocks: term i's block starts
+    // at z[i] with row stride ldz[i] and is scaled by zs[i].
+    struct ZBlocks {
+        std::vector<const double*> z;
+        std::vector<int64_t> ldz;
+        std::vector<double> zs;
+    };
+
+    // S(rows x nb) = sum_i Z_i W^(i)_{k+1}(:, c0:c0+nb), S column-major (ld);
+    // W is stored transposed (entry (b, c) at c * ld + b).
+    void sketch_gemm(int k, const ZBlocks& zb, int rows, int64_t c0, int nb, double* S, int64_t ld) {
+        for (int i = 0; i < x.m(); ++i) {
+            const TermW& tm = tw[i];
+            const int K = (int)x.sh[i].r[k];
+            const int sl = tm.sl[k + 1];
+            const int64_t ss = tm.ss[k + 1], wl = tm.ld[k + 1], off = c0 * wl;
+            const double beta = i > 0 ? 1.0 : 0.0;
+            const double* Z = zb.z[i];
+            const int64_t lz = zb.ldz[i];
+            const double al = zb.zs[i];
+            if (prec == 0)
+                gemm(ws, st, rows, nb, K, Z, lz, 1, static_cast<const double*>(wk(i, k + 1)) + off, 1, wl, S,
+                     1, ld, al, beta, nullptr, nullptr, nullptr, sl, ss);
+            else if (prec == 1)
+                gemm(ws, st, rows, nb, K, Z, lz, 1, nullptr, 1, wl, S, 1, ld, al, beta,
+                     static_cast<const float*>(wk(i, k + 1)) + off, cexp(i, k + 1) + c0, nullptr, sl, ss);
+            else
+                gemm(ws, st, rows, nb, K, Z, lz, 1, nullptr, 1, wl, S, 1, ld, al, beta, nullptr,
+                     cexp(i, k + 1) + c0, static_cast<const unsigned short*>(wk(i, k + 1)) + off, sl, ss);
+        }
     }
 };
+
+// Z blocks of mode k: the terms' first cores (with their weights) at k = 1,
+// else column blocks of the formal V(Y_k) held in ycur (row stride R_k).
+Sketch::ZBlocks z_blocks(const Summands& x, int k, const double* ycur) {
+    Sketch::ZBlocks zb;
+    for (int i = 0; i < x.m(); ++i) {
+        if (k == 1) {
+            zb.z.push_back(x.cores[i][0]);
+            zb.ldz.push_back(x.sh[i].r[1]);
+            zb.zs.push_back(x.w[i]);
+        } else {
+            zb.z.push_back(ycur + x.off[i][k]);
+            zb.ldz.push_back(x.fs.r[k]);
+            zb.zs.push_back(1.0);
+        }
+    }
+    return zb;
+}
+
+// M(lk x R_k, row stride R_k) = Q^T Z, block by block.
+void project(Workspace& ws, hipStream_t st, const Summands& x, const Sketch::ZBlocks& zb, int k,
+             const double* Q, int rows, int lk, double* M) {
+    const int64_t R = x.fs.r[k];
+    for (int i = 0; i < x.m(); ++i)
+        gemm(ws, st, lk, (int)x.sh[i].r[k], rows, Q, rows, 1, zb.z[i], zb.ldz[i], 1, M + x.off[i][k], R, 1,
+             zb.zs[i], 0.0);
+}
+
+// Formal Y_{k+1} = M H(X_{k+1}): term i's block of M times its core k+1,
+// written into the term's column block of Y_{k+1} (or, for the last core,
+// summed).  dst is lk x n_{k+1} x R_{k+1} row-major.
+void next_core(Workspace& ws, hipStream_t st, const Summands& x, int k, const double* M, int lk,
+               double* dst) {
+    const Shape& fs = x.fs;
+    const int d = fs.d;
+    const int64_t R = fs.r[k], R1 = fs.r[k + 1], n1 = fs.n[k];
+    for (int i = 0; i < x.m(); ++i) {
+        const int64_t ri = x.sh[i].r[k], ri1 = x.sh[i].r[k + 1];
+        const int nn = (int)(n1 * ri1);
+        GemmArgs g{};
+        g.M = lk;
+        g.N = nn;
+        g.K = (int)ri;
+        g.A = M + x.off[i][k];
+        g.sam = R;
+        g.sak = 1;
+        g.B = x.cores[i][k];
+        g.sbk = nn;
+        g.sbn = 1;
+        g.alpha = 1.0;
+        if (k + 1 == d || x.m() == 1) {
+            g.C = dst;
+            g.scm = n1 * R1;
+            g.scn = 1;
+            g.beta = (k + 1 == d && i > 0) ? 1.0 : 0.0;
+        } else {
+            g.C = dst + x.off[i][k + 1];
+            g.scm = n1 * R1;
+            g.scn = 1;
+            g.cdiv = (int)ri1;
+            g.cs_hi = R1;
+            g.beta = 0.0;
+        }
+        gemm_args(ws, st, g);
+    }
+}
 
 // Right-to-left truncation pass (Remark 2) on caller cores in place.  tau >=
 // 0 selects the tail rule, else target ranks (host [d+1]).
@@ -454,6 +570,45 @@ Shape make_shape(int d, const int64_t* n, const int64_t* ranks) {
     return s;
 }
 
+Summands single_term(const Shape& s, const double* const* cores) {
+    Summands x;
+    x.fs = s;
+    x.sh.push_back(s);
+    x.cores.push_back(cores);
+    x.w.push_back(1.0);
+    x.off.push_back(std::vector<int64_t>(s.d + 1, 0));
+    return x;
+}
+
+Summands make_sum(const std::vector<Shape>& sh, const std::vector<const double* const*>& cores,
+                  const double* weights) {
+    if (sh.empty() || sh.size() != cores.size()) throw Error(-1, "a sum needs at least one term");
+    const int d = sh[0].d;
+    Summands x;
+    x.fs.d = d;
+    x.fs.n = sh[0].n;
+    x.fs.r.assign(d + 1, 0);
+    x.fs.r[0] = x.fs.r[d] = 1;
+    for (size_t i = 0; i < sh.size(); ++i) {
+        if (sh[i].d != d || sh[i].n != sh[0].n)
+            throw Error(-1, "all terms of a sum need the same order and mode sizes");
+        std::vector<int64_t> off(d + 1, 0);
+        for (int k = 1; k < d; ++k) {
+            off[k] = x.fs.r[k];
+            x.fs.r[k] += sh[i].r[k];
+            if (x.fs.r[k] > (1 << 16)) throw Error(-1, "summed rank out of range");
+        }
+        x.sh.push_back(sh[i]);
+        x.cores.push_back(cores[i]);
+        x.w.push_back(weights ? weights[i] : 1.0);
+        x.off.push_back(off);
+    }
+    for (int k = 0; k < d; ++k)
+        if (x.fs.r[k] * x.fs.n[k] * x.fs.r[k + 1] > ((int64_t)1 << 31))
+            throw Error(-6, "formal core too large (more than 2^31 elements)");
+    return x;
+}
+
 std::vector<int64_t> rank_caps(const Shape& s) {
     std::vector<int64_t> c(s.d + 1, 1);
     for (int k = 1; k < s.d; ++k) c[k] = std::min(s.r[k], prod_capped(s.n, k, INT64_MAX / 4));
@@ -463,7 +618,8 @@ std::vector<int64_t> rank_caps(const Shape& s) {
 // ---------------------------------------------------------------------------
 // Workspace estimate
 // ---------------------------------------------------------------------------
-size_t workspace_bytes(const Shape& s, int64_t ell_max, int prec) {
+size_t workspace_bytes(const Summands& x, int64_t ell_max, int prec) {
+    const Shape& s = x.fs;
     const int d = s.d;
     const std::vector<int64_t> cap = rank_caps(s);
     std::vector<int64_t> l(d + 1, 1);
@@ -485,12 +641,14 @@ size_t workspace_bytes(const Shape& s, int64_t ell_max, int prec) {
         maxrows = std::max(maxrows, l[k - 1] * s.n[k - 1]);
         if (k >= 2) {
             b += (size_t)s.n[k - 1] * lcap * 8;       // Omega
-            const int64_t sl = pc_slices(s.r[k - 1], s.r[k], prec);
-            b += (size_t)sl * ((s.r[k - 1] + 3) / 4 * 4) * lcap * esz;   // W slices
-            b += (size_t)sl * s.r[k - 1] * ((lcap + 63) / 64) * 4;       // exponent slots
+            for (const Shape& si : x.sh) {
+                const int64_t sl = pc_slices(si.r[k - 1], si.r[k], prec);
+                b += (size_t)sl * ((si.r[k - 1] + 3) / 4 * 4) * lcap * esz;  // W slices
+                b += (size_t)sl * si.r[k - 1] * ((lcap + 63) / 64) * 4;      // exponent slots
+            }
         }
     }
-    b += (size_t)(d + 2) * lcap * 4;                  // column exponents
+    b += (size_t)x.m() * (d + 2) * lcap * 4;          // column exponents
     b += 2 * (size_t)maxy * 8;                        // sweep ping-pong
     b += (size_t)maxrows * lcap * 8;                  // Q
     b += (size_t)lcap * rmax * 8 + (size_t)lcap * 64 * 8;  // M, residual block
@@ -499,11 +657,16 @@ size_t workspace_bytes(const Shape& s, int64_t ell_max, int prec) {
     return b + b / 8 + ((size_t)16 << 20);
 }
 
+size_t workspace_bytes(const Shape& s, int64_t ell_max, int prec) {
+    return workspace_bytes(single_term(s, nullptr), ell_max, prec);
+}
+
 // ---------------------------------------------------------------------------
 // Fixed rank (Sec. 3.2)
 // ---------------------------------------------------------------------------
-void round_fixed(const Shape& s, const double* const* cores, const int64_t* target, int64_t ell,
-                 uint64_t seed, const Options& o, OutCores& y, RoundInfo& info) {
+void round_fixed(const Summands& x, const int64_t* target, int64_t ell, uint64_t seed,
+                 const Options& o, OutCores& y, RoundInfo& info) {
+    const Shape& s = x.fs;
     const int d = s.d;
     if (ell < 1) throw Error(-1, "ell must be >= 1");
     if (ell > 64) throw Error(-6, "fixed-rank sketch size ell > 64 is not supported");
@@ -515,7 +678,7 @@ void round_fixed(const Shape& s, const double* const* cores, const int64_t* targ
     for (int k = 1; k < d; ++k) l[k] = std::min<int64_t>({ell, l[k - 1] * s.n[k - 1], s.r[k]});
     check_capacity(s, l, y);
 
-    Sketch sk(s, cores, seed, o.prec, ell, st, ws);
+    Sketch sk(x, seed, o.prec, ell, st, ws);
     sk.pass(2, ell);
 
     int64_t maxy = 0, maxrows = 0;
@@ -527,18 +690,17 @@ void round_fixed(const Shape& s, const double* const* cores, const int64_t* targ
     double* Q = ws.q.as<double>(maxrows * ell);
     double* M = ws.m.as<double>((size_t)ell * *std::max_element(s.r.begin(), s.r.end()));
 
-    const double* ycur = cores[0];
+    const double* ycur = nullptr;
     for (int k = 1; k < d; ++k) {
         const int rows = (int)(l[k - 1] * s.n[k - 1]);
-        const int cols = (int)s.r[k];
         const int lk = (int)l[k];
-        sk.sketch_gemm(k, ycur, rows, cols, 0, lk, Q, rows);
+        const Sketch::ZBlocks zb = z_blocks(x, k, ycur);
+        sk.sketch_gemm(k, zb, rows, 0, lk, Q, rows);
         qr(ws, st, Q, rows, lk, rows);
-        gemm(ws, st, lk, cols, rows, Q, rows, 1, ycur, cols, 1, M, cols, 1);
+        project(ws, st, x, zb, k, Q, rows, lk, M);
         launch_copy2d(Q, 1, rows, y.cores[k - 1], lk, 1, rows, lk, 1.0, st);
-        const int nn = (int)(s.n[k] * s.r[k + 1]);
         double* dst = (k == d - 1) ? y.cores[d - 1] : ybuf[k & 1];
-        gemm(ws, st, lk, nn, cols, M, cols, 1, cores[k], nn, 1, dst, nn, 1);
+        next_core(ws, st, x, k, M, lk, dst);
         ycur = dst;
     }
     for (int k = 0; k <= d; ++k) y.ranks[k] = l[k];
@@ -557,11 +719,17 @@ void round_fixed(const Shape& s, const double* const* cores, const int64_t* targ
     info.passes = sk.passes;
 }
 
+void round_fixed(const Shape& s, const double* const* cores, const int64_t* target, int64_t ell,
+                 uint64_t seed, const Options& o, OutCores& y, RoundInfo& info) {
+    round_fixed(single_term(s, cores), target, ell, seed, o, y, info);
+}
+
 // ---------------------------------------------------------------------------
 // Adaptive rank (Sec. 3.3)
 // ---------------------------------------------------------------------------
-void round_adaptive(const Shape& s, const double* const* cores, double tol, int64_t ell_block,
-                    uint64_t seed, const Options& o, OutCores& y, RoundInfo& info) {
+void round_adaptive(const Summands& x, double tol, int64_t ell_block, uint64_t seed,
+                    const Options& o, OutCores& y, RoundInfo& info) {
+    const Shape& s = x.fs;
     const int d = s.d;
     if (!(tol > 0.0)) throw Error(-1, "tol must be > 0");
     hipStream_t st = o.stream;
@@ -584,7 +752,7 @@ void round_adaptive(const Shape& s, const double* const* cores, double tol, int6
     // Output capacity check against the worst-case ranks.
     check_capacity(s, cap, y);
 
-    Sketch sk(s, cores, seed, o.prec, lcap, st, ws);
+    Sketch sk(x, seed, o.prec, lcap, st, ws);
     sk.pass(2, r0);
 
     int64_t bmax = 1;
@@ -607,7 +775,7 @@ void round_adaptive(const Shape& s, const double* const* cores, double tol, int6
         // Remark 1: ||X|| ~ ||V(X_1) W_2||_F / sqrt(r0).
         const int rows = (int)s.n[0];
         double* tmp = ws.sbuf.as<double>((size_t)rows * r0 + 64);
-        sk.sketch_gemm(1, cores[0], rows, (int)s.r[1], 0, (int)r0, tmp, rows);
+        sk.sketch_gemm(1, z_blocks(x, 1, nullptr), rows, 0, (int)r0, tmp, rows);
         nrmx = std::sqrt(sumsq(ws, st, tmp, 1, rows, rows, (int)r0) / (double)r0);
     }
     const double tau = tol * nrmx / std::sqrt((double)(d - 1));
@@ -616,14 +784,15 @@ void round_adaptive(const Shape& s, const double* const* cores, double tol, int6
     info.nrmx = nrmx;
     info.min_margin = INFINITY;
 
-    const double* ycur = cores[0];
+    const double* ycur = nullptr;
     int64_t lprev = 1;
     for (int k = 1; k < d; ++k) {
         const int rows = (int)(lprev * s.n[k - 1]);
         const int cols = (int)s.r[k];
         const int rbar = std::min(rows, cols);
         const int binit = std::max(1, std::min(rbar, (int)std::ceil(f_init * (double)rbar)));
-        sk.sketch_gemm(k, ycur, rows, cols, 0, binit, Q, rows);
+        const Sketch::ZBlocks zb = z_blocks(x, k, ycur);
+        sk.sketch_gemm(k, zb, rows, 0, binit, Q, rows);
         qr(ws, st, Q, rows, binit, rows);
         int ncq = binit;
         const int blk = ell_block > 0 ? (int)ell_block : (int)std::ceil(0.05 * (double)rbar);
@@ -635,7 +804,7 @@ void round_adaptive(const Shape& s, const double* const* cores, double tol, int6
                 sk.pass(k + 1, grow);
             }
             double* S = Q + (size_t)ncq * rows;  // candidate columns follow Q
-            sk.sketch_gemm(k, ycur, rows, cols, ncq, bb, S, rows);
+            sk.sketch_gemm(k, zb, rows, ncq, bb, S, rows);
             // S -= Q (Q^T S)
             gemm(ws, st, ncq, bb, rows, Q, rows, 1, S, 1, rows, T, bb, 1);
             gemm(ws, st, rows, bb, ncq, Q, 1, rows, T, bb, 1, S, 1, rows, -1.0, 1.0);
@@ -650,11 +819,10 @@ void round_adaptive(const Shape& s, const double* const* cores, double tol, int6
             ncq += bb;
         }
         const int lk = ncq;
-        gemm(ws, st, lk, cols, rows, Q, rows, 1, ycur, cols, 1, M, cols, 1);
+        project(ws, st, x, zb, k, Q, rows, lk, M);
         launch_copy2d(Q, 1, rows, y.cores[k - 1], lk, 1, rows, lk, 1.0, st);
-        const int nn = (int)(s.n[k] * s.r[k + 1]);
         double* dst = (k == d - 1) ? y.cores[d - 1] : ybuf[k & 1];
-        gemm(ws, st, lk, nn, cols, M, cols, 1, cores[k], nn, 1, dst, nn, 1);
+        next_core(ws, st, x, k, M, lk, dst);
         ycur = dst;
         y.ranks[k] = lk;
         lprev = lk;
@@ -668,6 +836,11 @@ void round_adaptive(const Shape& s, const double* const* cores, double tol, int6
     TTR_HIP(hipStreamSynchronize(st));
     info.passes = sk.passes;
     if (info.iterations == 0) info.min_margin = INFINITY;
+}
+
+void round_adaptive(const Shape& s, const double* const* cores, double tol, int64_t ell_block,
+                    uint64_t seed, const Options& o, OutCores& y, RoundInfo& info) {
+    round_adaptive(single_term(s, cores), tol, ell_block, seed, o, y, info);
 }
 
 // ---------------------------------------------------------------------------
@@ -703,14 +876,12 @@ void partial_contractions(const Shape& s, const double* const* cores, uint64_t s
     if (prec < 0 || prec > 2) throw Error(-6, "precision not supported for partial contractions");
     WsLease lease;
     Workspace& ws = *lease.ws;
-    Sketch sk(s, cores, seed, prec, ncols, st, ws, col0);
+    const Summands x = single_term(s, cores);
+    Sketch sk(x, seed, prec, ncols, st, ws, col0);
     sk.pass(t, ncols);
-    for (int k = t; k <= s.d; ++k) {
-        const void* wk = prec == 0 ? (const void*)sk.wd(k)
-                                   : (prec == 1 ? (const void*)sk.wf(k) : (const void*)sk.wh(k));
-        launch_w_export(prec, wk, sk.cexp(k), sk.w_ld[k], (int)s.r[k - 1], 0, (int)ncols, sk.w_sl[k],
-                        sk.w_ss[k], w[k - t], ncols, st);
-    }
+    for (int k = t; k <= s.d; ++k)
+        launch_w_export(prec, sk.wk(0, k), sk.cexp(0, k), sk.tw[0].ld[k], (int)s.r[k - 1], 0, (int)ncols,
+                        sk.tw[0].sl[k], sk.tw[0].ss[k], w[k - t], ncols, st);
     TTR_HIP(hipStreamSynchronize(st));
 }
 

@@ -35,6 +35,24 @@ struct OutCores {
     int orth = 0;    // written: 1 left, 2 right
 };
 
+// A TT given as a weighted sum of TTs with the same mode sizes (one term
+// for a plain TT).  The formal shape has the summed interior ranks: the
+// rounding of the sum is the rounding of the formal sum (first cores side
+// by side with the weights, block-diagonal middle cores, stacked last
+// cores), which is never assembled.
+struct Summands {
+    Shape fs;                                 // formal shape
+    std::vector<Shape> sh;                    // per term
+    std::vector<const double* const*> cores;  // per term: d device pointers
+    std::vector<double> w;                    // per term weight (first core)
+    std::vector<std::vector<int64_t>> off;    // per term: offsets in the formal ranks, [d+1]
+    int m() const { return (int)sh.size(); }
+};
+Summands single_term(const Shape& s, const double* const* cores);
+// weights: nullptr for all 1.
+Summands make_sum(const std::vector<Shape>& sh, const std::vector<const double* const*>& cores,
+                  const double* weights);
+
 Shape make_shape(int d, const int64_t* n, const int64_t* ranks);
 // c_k = min(r_k, n_1 ... n_k) (k = 0..d, c_0 = c_d = 1).
 std::vector<int64_t> rank_caps(const Shape& s);
@@ -42,7 +60,12 @@ std::vector<int64_t> rank_caps(const Shape& s);
 // Upper estimate of the device workspace one rounding of this shape uses:
 // ell_max > 0 for fixed rank with that sketch size, <= 0 for adaptive.
 size_t workspace_bytes(const Shape& s, int64_t ell_max, int prec);
+size_t workspace_bytes(const Summands& x, int64_t ell_max, int prec);
 
+void round_fixed(const Summands& x, const int64_t* target, int64_t ell, uint64_t seed,
+                 const Options& o, OutCores& y, RoundInfo& info);
+void round_adaptive(const Summands& x, double tol, int64_t ell_block, uint64_t seed,
+                    const Options& o, OutCores& y, RoundInfo& info);
 void round_fixed(const Shape& s, const double* const* cores, const int64_t* target, int64_t ell,
                  uint64_t seed, const Options& o, OutCores& y, RoundInfo& info);
 void round_adaptive(const Shape& s, const double* const* cores, double tol, int64_t ell_block,

@@ -138,3 +138,27 @@ def test_batch_and_server_validate_on_host():
     assert L.tt_result_copy(None, None, None) == -1
     L.tt_result_release(None)
     L.tt_server_destroy(None)
+
+
+def test_sum_capacity_and_validation_host_only():
+    import paper_2511_03598_amd as ttr
+    L = ttr.lib()
+    v1, k1 = _view(3, [4, 5, 6], [1, 2, 3, 1], [1, 2, 3])
+    v2, k2 = _view(3, [4, 5, 6], [1, 3, 4, 1], [4, 5, 6])
+    views = (ttr._View * 2)(v1, v2)
+    cap = (ctypes.c_int64 * 3)()
+    assert L.tt_sum_out_capacity(views, 2, None, cap) == 0
+    # formal ranks (1, 5, 7, 1), capped at (1, min(5,4), min(7,20), 1) = (1, 4, 7, 1)
+    assert list(cap) == [1 * 4 * 4, 4 * 5 * 7, 7 * 6 * 1]
+    assert L.tt_sum_out_capacity(views, 0, None, cap) == -1
+    bad, kb = _view(3, [4, 5, 7], [1, 2, 3, 1], [1, 2, 3])  # mode sizes differ
+    views_bad = (ttr._View * 2)(v1, bad)
+    assert L.tt_sum_out_capacity(views_bad, 2, None, cap) == -1
+    assert b"mode sizes" in L.tt_last_error()
+    outs = ttr._Out(3, (ctypes.c_int64 * 4)(), (ctypes.c_void_p * 3)(1, 2, 3), cap, 0)
+    w = (ctypes.c_double * 2)(1.0, float("nan"))
+    assert L.tt_round_sum_adaptive(views, 2, w, 1e-6, 4, 1, None, ctypes.byref(outs)) == -1
+    assert b"finite" in L.tt_last_error()
+    assert L.tt_round_sum_fixed(views, 2, None, None, 0, 1, None, ctypes.byref(outs)) == -1
+    assert L.tt_round_sum_adaptive(views, 2, None, 0.0, 4, 1, None, ctypes.byref(outs)) == -1
+    assert L.tt_round_sum_adaptive(views_bad, 2, None, 1e-6, 4, 1, None, ctypes.byref(outs)) == -1
