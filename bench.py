@@ -199,7 +199,7 @@ def main():
         "sketch_GBps": sketch_gbps,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic,
-                     "kernel": "partial contraction (pc_wide_kernel<float>)",
+                     "kernel": "partial contraction (pc_kernel<float>)",
                      "bytes_per_launch": pc_bytes / npc, "avg_launch_us": avg_launch_s * 1e6},
         "kernel_ms_per_step": {k: v[1] / args.steps for k, v in kt.items()},
         "wall_s": wall,
