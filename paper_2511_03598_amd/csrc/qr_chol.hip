@@ -2,11 +2,13 @@
 // ill-conditioned panels, all decided on the device.
 //
 //   gram    : per-block partial Grams G = S^T S (MFMA), written to a buffer;
-//   chol    : one workgroup sums the partials in a fixed order, factors
-//             G = R^T R (Cholesky), forms R^{-1} in the same sweep and sets
-//             the route flags;
-//   apply   : Q_next = Q_prev R^{-1} per row block (MFMA), plus the partial
-//             Grams of Q_next when another pass follows.
+//   reduce  : sums the partials in a fixed order (16 workgroups);
+//   apply   : every workgroup factors the summed Gram, G = R^T R
+//             (Cholesky), and forms R^{-1} in LDS -- the same deterministic
+//             computation in each, so all take the same route -- then
+//             Q_next = Q_prev R^{-1} for its row block (MFMA), plus the
+//             partial Grams of Q_next when another pass follows.  Workgroup
+//             0 records R and the route flags for the kernels after it.
 //
 // Pass 1 first tries the plain Cholesky and certifies the panel: every pivot
 // must keep at least 1e-10 of its column's squared norm, i.e. the
@@ -36,8 +38,8 @@ struct CqDev {
     double* q1;     // m x b temporaries (ld m)
     double* q2;
     double* gpart;  // P x 64 x 64 partial Grams
-    double* rinv;   // 3 x 64 x 64 R^{-1} per pass (row-major, identity-padded)
-    double* rfac;   // 3 x 64 x 64 R per pass
+    double* g;      // 64 x 64 summed Gram of the current pass
+    double* rfac;   // 3 x 64 x 64 R per pass (row-major, identity-padded)
     double* r_out;  // optional b x b column-major R of the panel
     int* flags;
 };
@@ -62,25 +64,35 @@ __device__ __forceinline__ void gram_tile(const double* T, double4_t acc[4]) {
 }
 
 // T (TB rows x 64 cols, zero padded) <- rows [r, r_end) of the column-major
-// panel.  Indices are clamped so every load is issued unconditionally (a
-// masked load would serialise on its own wait); the padding is selected
-// afterwards.  256 threads, 16 loads each.
-__device__ __forceinline__ void load_tile(const double* src, int ld, int r, int r_end, int b,
-                                          double* T) {
+// panel, in two halves so the loads can be issued early.  Indices are
+// clamped so every load is issued unconditionally (a masked load would
+// serialise on its own wait); the padding is selected when storing.  256
+// threads, 16 loads each.
+__device__ __forceinline__ void load_regs(const double* src, int ld, int r, int r_end, int b,
+                                          double (&v)[16]) {
     const int i = threadIdx.x & (TB - 1), c0 = threadIdx.x / TB;
     const int row = min(r + i, r_end - 1);
-    double v[16];
 #pragma unroll
     for (int e = 0; e < 16; ++e) {
         const int c = min(c0 + 4 * e, b - 1);
         v[e] = src[(size_t)c * ld + row];
     }
+}
+__device__ __forceinline__ void store_regs(double* T, const double (&v)[16], int r, int r_end,
+                                           int b) {
+    const int i = threadIdx.x & (TB - 1), c0 = threadIdx.x / TB;
     const bool row_ok = (r + i) < r_end;
 #pragma unroll
     for (int e = 0; e < 16; ++e) {
         const int c = c0 + 4 * e;
         T[i * LDT + c] = (row_ok && c < b) ? v[e] : 0.0;
     }
+}
+__device__ __forceinline__ void load_tile(const double* src, int ld, int r, int r_end, int b,
+                                          double* T) {
+    double v[16];
+    load_regs(src, ld, r, r_end, b, v);
+    store_regs(T, v, r, r_end, b);
 }
 
 __device__ __forceinline__ void store_partial(double* gp, const double4_t acc[4]) {
@@ -113,191 +125,259 @@ __global__ void __launch_bounds__(256) cq_gram_kernel(CqDev q) {
     store_partial(q.gpart + (size_t)blockIdx.x * 4096, acc);
 }
 
-// Cholesky G = R^T R of the LDS matrix G0 (64 x LDT, identity-padded beyond
-// b, `shift` added to the first b diagonal entries) together with R^{-1},
-// 512 threads.  Lane i of every wave is row i.  Waves 0-3 hold columns
-// 16w .. 16w+15 of G; waves 4-7 hold the same columns of an identity matrix
-// A that the elimination turns into L^{-1} (L = R^T), so R^{-1} = (L^{-1})^T
-// comes out of the same sweep.  Step k (k < b; padding steps are no-ops):
-//   - wave k/16 publishes column k of G, lane k of each A wave publishes its
-//     part of row k of A (double-buffered LDS, one barrier per step);
-//   - L(i,k) = G(i,k)/sqrt(G(k,k)); G waves right of the pivot update their
-//     columns j > k: G(i,j) -= L(i,k) L(j,k) (the column test is static
-//     within the unrolled block, waves left of the pivot are done and skip);
-//   - A waves: row k becomes A_k / L(k,k) and rows i > k lose L(i,k) times it.
-// Rows above the pivot keep stale values in the upper triangle of G, which
-// the factor never reads.  Writes R (row-major, identity-padded) to rfac and
-// R^{-1} to rinv.  Returns 1 (block-wide) if a pivot falls to <= rel * (its
-// original value) or is not finite; the owner of the diagonal checks it.
-__device__ int chol_inv(const double* G0, double shift, double rel, int b, double* colbuf,
-                        double* rowbuf, double* rfac, double* rinv) {
-    const int tid = threadIdx.x, i = tid & 63, w = tid >> 6;
-    const bool gw = w < 4;
-    const int cb0 = 16 * (w & 3);  // first column of this wave's block
-    double g[16];
-#pragma unroll
-    for (int jj = 0; jj < 16; ++jj) {
-        const int j = cb0 + jj;
-        g[jj] = gw ? G0[i * LDT + j] + ((i == j && i < b) ? shift : 0.0) : (i == j ? 1.0 : 0.0);
+// ---------------------------------------------------------------------------
+// Cholesky G + sI = L L^T (L = R^T) and X = L^{-1} of the 64 x 64 Gram, in
+// LDS, by 256 threads (4 waves), blocked by 16 columns; lane i is row i.
+//   panel kb: wave kb factors columns 16kb .. 16kb+15 for all rows with no
+//     barrier.  Per pivot k the column-k values of the 16 diagonal-block rows
+//     go through LDS to every lane (the LDS accesses of one wave complete in
+//     order), L(i,k) = a(i,k) / sqrt(d_k) and a(i,j) -= L(i,k) L(j,k).  The
+//     16 diagonal entries are also carried as uniform values updated by the
+//     same operations as their owners' (so bit-identical), which lets the
+//     next pivot's reciprocal square root start before the next exchange;
+//   one barrier; then wave w > kb subtracts the panel's rank-16 product from
+//     its own block column (MFMA) while wave kb inverts its diagonal block
+//     (lane c: column c of L_kk^{-1} by forward substitution, no exchange);
+//   after the last panel the off-diagonal blocks of X follow one block
+//     diagonal at a time from X_ij = -X_ii sum_{k=j}^{i-1} L_ik X_kj (MFMA).
+// Padding beyond b is the identity, so L and X are the identity there; only
+// the ceil(b/16) panels that hold columns of G are factored.
+// ---------------------------------------------------------------------------
+struct __align__(16) FactorLds {
+    double L[64 * LDT];  // working matrix, then L (zero above the diagonal)
+    double X[64 * LDT];  // L^{-1} (zero above the diagonal)
+    double col[2][64];   // column exchange of the panel wave
+    double d0[64];       // diagonal of G + sI (pivot certificate)
+    double sinv[64];     // 1 / L(k,k)
+};
+
+// L <- G + sI (first b diagonal entries shifted), identity-padded; X <- 0
+// with identity diagonal blocks past the factored panels.
+__device__ __forceinline__ void factor_init(const double* G, double shift, int b, int nkb,
+                                            FactorLds& F) {
+    for (int t = threadIdx.x; t < 64 * 64; t += 256) {
+        const int i = t >> 6, j = t & 63;
+        double v = (i < b && j < b) ? G[t] : (i == j ? 1.0 : 0.0);
+        if (i == j && i < b) v += shift;
+        F.L[i * LDT + j] = v;
+        F.X[i * LDT + j] = (i == j && i >= 16 * nkb) ? 1.0 : 0.0;
+        if (i == j) F.d0[i] = v;
     }
-    const double d0 = G0[i * LDT + i] + (i < b ? shift : 0.0);
-    int bad = 0;
-#pragma unroll 1
-    for (int kb = 0; kb < 4; ++kb) {
-#pragma unroll
-        for (int kk = 0; kk < 16; ++kk) {
-            const int k = 16 * kb + kk;
-            if (k < b) {  // uniform
-                double* cb = colbuf + (kk & 1) * 64;
-                double* rb = rowbuf + (kk & 1) * 64;
-                if (w == kb) cb[i] = g[kk];
-                if (!gw && i == k) {
-                    double2_t* dst = reinterpret_cast<double2_t*>(rb + cb0);
-#pragma unroll
-                    for (int h = 0; h < 8; ++h) dst[h] = double2_t{g[2 * h], g[2 * h + 1]};
-                }
-                __syncthreads();
-                const double dkk = cb[k];
-                const double ci = cb[i];
-                if (gw) {
-                    if (w >= kb) {  // uniform
-                        double cv[16];
-                        const double2_t* src = reinterpret_cast<const double2_t*>(cb + cb0);
-#pragma unroll
-                        for (int h = 0; h < 8; ++h) {
-                            const double2_t v = src[h];
-                            cv[2 * h] = v[0];
-                            cv[2 * h + 1] = v[1];
-                        }
-                        const double rinv_k = rsqrt_nr(fmax(dkk, 1e-300));
-                        const double li = ci * rinv_k;
-                        const double t = li * rinv_k;
-                        if (w > kb) {
-#pragma unroll
-                            for (int jj = 0; jj < 16; ++jj) g[jj] = fma(-t, cv[jj], g[jj]);
-                        } else {
-#pragma unroll
-                            for (int jj = kk + 1; jj < 16; ++jj) g[jj] = fma(-t, cv[jj], g[jj]);
-                            g[kk] = li;
-                            if (i == k && !(d0 > 0.0 && dkk > rel * d0 && dkk < INFINITY)) bad = 1;
-                        }
-                    }
-                } else {
-                    double x[16];
-                    const double2_t* src = reinterpret_cast<const double2_t*>(rb + cb0);
-#pragma unroll
-                    for (int h = 0; h < 8; ++h) {
-                        const double2_t v = src[h];
-                        x[2 * h] = v[0];
-                        x[2 * h + 1] = v[1];
-                    }
-                    const double rinv_k = rsqrt_nr(fmax(dkk, 1e-300));
-                    const double c1 = (i == k) ? rinv_k : 1.0;
-                    const double c2 = (i > k) ? ci * rinv_k * rinv_k : 0.0;
-#pragma unroll
-                    for (int jj = 0; jj < 16; ++jj) g[jj] = fma(-c2, x[jj], g[jj] * c1);
-                }
-            }
-        }
-    }
-    // R(j, i) = L(i, j) for i >= j; R^{-1}(j, i) = L^{-1}(i, j)
-#pragma unroll
-    for (int jj = 0; jj < 16; ++jj) {
-        const int j = cb0 + jj;
-        if (gw)
-            rfac[j * 64 + i] = (i >= j) ? g[jj] : 0.0;
-        else
-            rinv[j * 64 + i] = (i >= j) ? g[jj] : 0.0;
-    }
-    return __syncthreads_or(bad);
+    __syncthreads();
 }
 
-// One workgroup: sum the P partial Grams (fixed order), factor, invert.
-//   pass 0: plain Cholesky with the 1e-10 certificate; if it fails, redo it
-//           on G + sI and mark the shifted route;
-//   pass 1: plain Cholesky of Q1^T Q1 (fallback flag on breakdown);
-//   pass 2: only on the shifted route, Cholesky of Q2^T Q2.
-__global__ void __launch_bounds__(512) cq_chol_kernel(CqDev q, int pass) {
-    if (q.flags[0]) return;
-    if (pass == 2 && !q.flags[1]) return;
-    __shared__ double G0[64 * LDT];
-    __shared__ __align__(16) double colbuf[128];
-    __shared__ __align__(16) double rowbuf[128];
-    const int tid = threadIdx.x;
-    const int b = q.b;
-    // 8 consecutive entries per thread, partials summed in order p = 0..P-1
-    {
-        const int i = tid >> 3, j0 = (tid & 7) * 8;
-        const int ic = min(i, b - 1);
-        double acc[8];
+// Panel kb by its own wave.  Returns 1 if a pivot falls to <= rel * (its
+// value in G + sI) or is not finite.
+__device__ __forceinline__ int factor_panel(FactorLds& F, int kb, double rel) {
+    const int i = threadIdx.x & 63;
+    const int c0 = 16 * kb;
+    double a[16], dg[16], dd0[16];
 #pragma unroll
-        for (int jj = 0; jj < 8; ++jj) acc[jj] = 0.0;
-#pragma unroll 4
-        for (int p = 0; p < q.P; ++p) {
-            const double2_t* src =
-                reinterpret_cast<const double2_t*>(q.gpart + (size_t)p * 4096 + ic * 64 + j0);
+    for (int jj = 0; jj < 16; ++jj) {
+        a[jj] = F.L[i * LDT + c0 + jj];
+        dg[jj] = F.L[(c0 + jj) * LDT + c0 + jj];
+        dd0[jj] = F.d0[c0 + jj];
+    }
+    int bad = 0;
+    double sv = 0.0;  // lane jj < 16 keeps 1/L(c0+jj, c0+jj)
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const double2_t x = src[v];
-                acc[2 * v] += x[0];
-                acc[2 * v + 1] += x[1];
-            }
+    for (int kk = 0; kk < 16; ++kk) {
+        const double piv = dg[kk];
+        bad |= !(dd0[kk] > 0.0 && piv > rel * dd0[kk] && piv < INFINITY);
+        const double sk = rsqrt_nr(fmax(piv, 1e-300));
+        sv = (i == kk) ? sk : sv;
+        double* cb = F.col[kk & 1];
+        cb[i] = a[kk];
+        __builtin_amdgcn_wave_barrier();
+        double c[16];
+#pragma unroll
+        for (int jj = kk + 1; jj < 16; ++jj) c[jj] = cb[c0 + jj];
+        const double li = a[kk] * sk;
+        const double t = li * sk;
+        a[kk] = li;
+#pragma unroll
+        for (int jj = kk + 1; jj < 16; ++jj) {
+            a[jj] = fma(-t, c[jj], a[jj]);
+            dg[jj] = fma(-((c[jj] * sk) * sk), c[jj], dg[jj]);
+        }
+    }
+#pragma unroll
+    for (int jj = 0; jj < 16; ++jj) F.L[i * LDT + c0 + jj] = (i >= c0 + jj) ? a[jj] : 0.0;
+    if (i < 16) F.sinv[c0 + i] = sv;
+    return bad;
+}
+
+// Wave w > kb: block column w (rows 16w..63) -= L(:, panel kb) L(w rows, panel kb)^T.
+__device__ __forceinline__ void update_block_column(FactorLds& F, int kb, int w) {
+    const int lane = threadIdx.x & 63, li = lane & 15, lg = lane >> 4;
+    const int p0 = 16 * kb, c0 = 16 * w;
+    for (int ti = w; ti < 4; ++ti) {
+        double4_t acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int k4 = 0; k4 < 16; k4 += 4) {
+            const double av = F.L[(16 * ti + li) * LDT + p0 + k4 + lg];
+            const double bv = F.L[(c0 + li) * LDT + p0 + k4 + lg];
+            acc = mfma_f64_16x16x4(av, bv, acc);
         }
 #pragma unroll
-        for (int jj = 0; jj < 8; ++jj) {
-            const int j = j0 + jj;
-            G0[i * LDT + j] = (i < b && j < b) ? acc[jj] : ((i == j) ? 1.0 : 0.0);
+        for (int v = 0; v < 4; ++v) F.L[(16 * ti + mfma_row_f64(lg, v)) * LDT + c0 + li] -= acc[v];
+    }
+}
+
+// Wave kb: X_kk = L_kk^{-1}; lane c solves L_kk x = e_c.
+__device__ __forceinline__ void invert_diag(FactorLds& F, int kb) {
+    const int lane = threadIdx.x & 63, c = lane & 15;
+    const int c0 = 16 * kb;
+    double x[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        const double* lr = F.L + (c0 + r) * LDT + c0;
+        double acc0 = (r == c) ? 1.0 : 0.0, acc1 = 0.0;
+#pragma unroll
+        for (int j = 0; j < r; ++j) {
+            if (j & 1)
+                acc1 = fma(-lr[j], x[j], acc1);
+            else
+                acc0 = fma(-lr[j], x[j], acc0);
+        }
+        x[r] = (acc0 + acc1) * F.sinv[c0 + r];
+    }
+    if (lane < 16) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) F.X[(c0 + r) * LDT + c0 + c] = x[r];
+    }
+}
+
+// Off-diagonal blocks of X, block diagonal lev = 1, 2, 3 in turn; wave w
+// computes X(w+lev, w).  Ends with a barrier.
+__device__ __forceinline__ void invert_offdiag(FactorLds& F, int nkb) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, li = lane & 15, lg = lane >> 4;
+    for (int lev = 1; lev < nkb; ++lev) {
+        __syncthreads();
+        const int j = w, i = w + lev;
+        if (i < nkb) {
+            double4_t u = {0.0, 0.0, 0.0, 0.0};  // sum_k L_ik X_kj
+            for (int k = j; k < i; ++k) {
+#pragma unroll
+                for (int k4 = 0; k4 < 16; k4 += 4) {
+                    const double av = F.L[(16 * i + li) * LDT + 16 * k + k4 + lg];
+                    const double bv = F.X[(16 * k + k4 + lg) * LDT + 16 * j + li];
+                    u = mfma_f64_16x16x4(av, bv, u);
+                }
+            }
+            // U goes to the block's own place, then X_ij = -X_ii U
+            double* xij = F.X + 16 * i * LDT + 16 * j;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) xij[mfma_row_f64(lg, v) * LDT + li] = u[v];
+            __builtin_amdgcn_wave_barrier();
+            double4_t x = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int k4 = 0; k4 < 16; k4 += 4) {
+                const double av = F.X[(16 * i + li) * LDT + 16 * i + k4 + lg];
+                const double bv = xij[(k4 + lg) * LDT + li];
+                x = mfma_f64_16x16x4(av, bv, x);
+            }
+            __builtin_amdgcn_wave_barrier();
+#pragma unroll
+            for (int v = 0; v < 4; ++v) xij[mfma_row_f64(lg, v) * LDT + li] = -x[v];
         }
     }
     __syncthreads();
-    double* rfac = q.rfac + (size_t)pass * 4096;
-    double* rinv = q.rinv + (size_t)pass * 4096;
-    // pass 0 retries once with the shift when the certificate fails
+}
+
+// Returns 1 (block-wide) if the certificate or the factorization fails.
+__device__ int chol_factor(const double* G, double shift, double rel, int b, FactorLds& F) {
+    const int nkb = (b + 15) / 16;
+    factor_init(G, shift, b, nkb, F);
+    const int w = threadIdx.x >> 6;
+    int bad = 0;
+    for (int kb = 0; kb < nkb; ++kb) {
+        if (w == kb) bad |= factor_panel(F, kb, rel);
+        __syncthreads();
+        if (w == kb)
+            invert_diag(F, kb);
+        else if (w > kb)
+            update_block_column(F, kb, w);
+    }
+    invert_offdiag(F, nkb);
+    return __syncthreads_or(bad);
+}
+
+// Sum of the P partial Grams in the order p = 0..P-1.  Pass 3 runs only on
+// the shifted route.
+__global__ void __launch_bounds__(256) cq_reduce_kernel(CqDev q, int pass) {
+    if (q.flags[0]) return;
+    if (pass == 3 && !q.flags[1]) return;
+    const int e = blockIdx.x * 256 + threadIdx.x;
+    double s = 0.0;
+#pragma unroll 8
+    for (int p = 0; p < q.P; ++p) s += q.gpart[(size_t)p * 4096 + e];
+    q.g[e] = s;
+}
+
+// Pass p (1..3): factor the pass's Gram (pass 1 with the certificate and,
+// if it fails, the shifted retry; pass 2 with the 0.5 certificate on the
+// plain route; pass 3 only on the shifted route), then out = src * R^{-1}
+// per row block (MFMA) with the partial Grams of out when another pass
+// follows.  Pass 1 reads S and writes Q1; pass 2 reads Q1 and writes Q2 or,
+// on the plain route, the final Q into the panel; pass 3 reads Q2 and writes
+// the final Q.  On a failed factorization nothing is written but the flag.
+__global__ void __launch_bounds__(256) cq_apply_kernel(CqDev q, int pass) {
+    if (q.flags[0]) return;
+    const bool shifted_in = q.flags[1] != 0;  // meaningful from pass 2 on
+    if (pass == 3 && !shifted_in) return;
+    __shared__ FactorLds F;
+    __shared__ double T[TB * LDT];
+    const int tid = threadIdx.x, b = q.b;
+    const double* src = (pass == 1) ? q.a : (pass == 2 ? q.q1 : q.q2);
+    const int lds = (pass == 1) ? q.lda : q.m;
+    int r0, r1;
+    block_rows(q, blockIdx.x, r0, r1);
+    // the first row tile is requested before the factorization, which hides
+    // its latency
+    double v[16];
+    if (r0 < r1) load_regs(src, lds, r0, r1, b, v);
+
     double shift = 0.0;
-    double rel = (pass == 0) ? 1e-10 : ((pass == 1 && !q.flags[1]) ? 0.5 : 0.0);
+    double rel = (pass == 1) ? 1e-10 : ((pass == 2 && !shifted_in) ? 0.5 : 0.0);
     int bad;
 #pragma unroll 1
     for (int attempt = 0;; ++attempt) {
-        bad = chol_inv(G0, shift, rel, b, colbuf, rowbuf, rfac, rinv);
-        if (pass != 0 || !bad || attempt == 1) break;
+        bad = chol_factor(q.g, shift, rel, b, F);
+        if (pass != 1 || !bad || attempt == 1) break;
         double tr = 0.0;
-        for (int j = 0; j < b; ++j) tr += G0[j * LDT + j];
+        for (int j = 0; j < b; ++j) tr += F.d0[j];
         shift = 11.0 * ((double)q.m * b + (double)b * (b + 1)) * 1.1102230246251565e-16 * tr;
         rel = 0.0;
+        __syncthreads();  // d0 is read before the retry overwrites it
     }
-    if (pass == 0 && tid == 0) q.flags[1] = (shift > 0.0) ? 1 : 0;
-    if (tid == 0 && bad) q.flags[0] = 1;
-}
+    const bool shifted = (pass == 1) ? (shift > 0.0) : shifted_in;
+    if (blockIdx.x == 0) {
+        if (tid == 0 && bad) q.flags[0] = 1;
+        if (tid == 0 && pass == 1) q.flags[1] = shifted ? 1 : 0;
+        double* rf = q.rfac + (size_t)(pass - 1) * 4096;  // R(j, i) = L(i, j)
+        for (int t = tid; t < 64 * 64; t += 256) {
+            const int j = t >> 6, i = t & 63;
+            rf[t] = (i >= j) ? F.L[i * LDT + j] : 0.0;
+        }
+    }
+    if (bad) return;  // block-uniform; the panel stays as it was
 
-// out = src * Rinv(pass) per row block (MFMA); with GRAM, also the partial
-// Grams of out.  pass 1 reads S and writes Q1; pass 2 reads Q1 and writes Q2
-// or, when the route is not shifted, the final Q into the panel; pass 3
-// (shifted route only) reads Q2 and writes the final Q.
-__global__ void __launch_bounds__(256) cq_apply_kernel(CqDev q, int pass) {
-    if (q.flags[0]) return;
-    const bool shifted = q.flags[1] != 0;
-    if (pass == 3 && !shifted) return;
     const bool final_pass = (pass == 3) || (pass == 2 && !shifted);
     const bool gram = !final_pass;
-    __shared__ double T[TB * LDT];
-    __shared__ double Ri[64 * LDT];
-    const double* src = (pass == 1) ? q.a : (pass == 2 ? q.q1 : q.q2);
-    const int lds = (pass == 1) ? q.lda : q.m;
     double* dst = final_pass ? q.a : (pass == 1 ? q.q1 : q.q2);
     const int ldd = final_pass ? q.lda : q.m;
-    const double* rinv = q.rinv + (size_t)(pass - 1) * 4096;
-    for (int t = threadIdx.x; t < 64 * 64; t += 256) Ri[(t >> 6) * LDT + (t & 63)] = rinv[t];
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int lane = tid & 63, w = tid >> 6;
     const int li = lane & 15, lg = lane >> 4;
-    int r0, r1;
-    block_rows(q, blockIdx.x, r0, r1);
     double4_t gacc[4];
 #pragma unroll
     for (int nb = 0; nb < 4; ++nb) gacc[nb] = double4_t{0, 0, 0, 0};
     for (int r = r0; r < r1; r += TB) {
+        if (r > r0) load_regs(src, lds, r, r1, b, v);
         __syncthreads();
-        load_tile(src, lds, r, r1, q.b, T);
+        store_regs(T, v, r, r1, b);
         __syncthreads();
+        // R^{-1}(k, c) = X(c, k)
         double4_t acc[4];
 #pragma unroll
         for (int nb = 0; nb < 4; ++nb) acc[nb] = double4_t{0, 0, 0, 0};
@@ -306,18 +386,18 @@ __global__ void __launch_bounds__(256) cq_apply_kernel(CqDev q, int pass) {
             const double av = T[(w * 16 + li) * LDT + kk + lg];
 #pragma unroll
             for (int nb = 0; nb < 4; ++nb)
-                acc[nb] = mfma_f64_16x16x4(av, Ri[(kk + lg) * LDT + nb * 16 + li], acc[nb]);
+                acc[nb] = mfma_f64_16x16x4(av, F.X[(nb * 16 + li) * LDT + kk + lg], acc[nb]);
         }
         __syncthreads();
 #pragma unroll
         for (int nb = 0; nb < 4; ++nb)
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int i = w * 16 + mfma_row_f64(lg, v), c = nb * 16 + li;
+            for (int vv = 0; vv < 4; ++vv) {
+                const int i = w * 16 + mfma_row_f64(lg, vv), c = nb * 16 + li;
                 const int row = r + i;
                 const bool ok = (row < r1 && c < q.b);
-                if (ok) dst[(size_t)c * ldd + row] = acc[nb][v];
-                T[i * LDT + c] = ok ? acc[nb][v] : 0.0;
+                if (ok) dst[(size_t)c * ldd + row] = acc[nb][vv];
+                T[i * LDT + c] = ok ? acc[nb][vv] : 0.0;
             }
         if (gram) {
             __syncthreads();
@@ -369,9 +449,12 @@ __global__ void __launch_bounds__(256) cq_rout_kernel(CqDev q) {
 
 }  // namespace
 
+namespace {
+int cq_blocks(int m) { return std::max(1, std::min(64, ceil_div(m, TB))); }
+}  // namespace
+
 size_t cq_workspace_doubles(int m, int b) {
-    const int P = std::max(1, std::min(16, ceil_div(m, 128)));
-    return 2 * (size_t)m * b + (size_t)P * 4096 + 6 * 4096 + 64;
+    return 2 * (size_t)m * b + (size_t)cq_blocks(m) * 4096 + 4 * 4096 + 64;
 }
 
 void launch_cq(double* a, int m, int b, int lda, double* r_out, double* ws, int* flags,
@@ -380,19 +463,19 @@ void launch_cq(double* a, int m, int b, int lda, double* r_out, double* ws, int*
     q.m = m;
     q.b = b;
     q.lda = lda;
-    q.P = std::max(1, std::min(16, ceil_div(m, 128)));
+    q.P = cq_blocks(m);
     q.a = a;
     q.q1 = ws;
     q.q2 = ws + (size_t)m * b;
     q.gpart = q.q2 + (size_t)m * b;
-    q.rinv = q.gpart + (size_t)q.P * 4096;
-    q.rfac = q.rinv + 3 * 4096;
+    q.g = q.gpart + (size_t)q.P * 4096;
+    q.rfac = q.g + 4096;
     q.r_out = r_out;
     q.flags = flags;
     hipLaunchKernelGGL(cq_gram_kernel, dim3(q.P), dim3(256), 0, s, q);
     TTR_CHECK_LAUNCH();
     for (int pass = 1; pass <= 3; ++pass) {
-        hipLaunchKernelGGL(cq_chol_kernel, dim3(1), dim3(512), 0, s, q, pass - 1);
+        hipLaunchKernelGGL(cq_reduce_kernel, dim3(16), dim3(256), 0, s, q, pass);
         TTR_CHECK_LAUNCH();
         hipLaunchKernelGGL(cq_apply_kernel, dim3(q.P), dim3(256), 0, s, q, pass);
         TTR_CHECK_LAUNCH();
