@@ -2,7 +2,7 @@
 // ill-conditioned panels, all decided on the device.
 //
 //   gram    : per-block partial Grams G = S^T S (MFMA), written to a buffer;
-//   reduce  : sums the partials in a fixed order (16 workgroups);
+//   reduce  : sums the partials in a fixed order (64 workgroups);
 //   apply   : every workgroup factors the summed Gram, G = R^T R
 //             (Cholesky), and forms R^{-1} in LDS -- the same deterministic
 //             computation in each, so all take the same route -- then
@@ -131,33 +131,41 @@ __global__ void __launch_bounds__(256) cq_gram_kernel(CqDev q) {
 //   panel kb: wave kb factors columns 16kb .. 16kb+15 for all rows with no
 //     barrier.  Per pivot k the column-k values of the 16 diagonal-block rows
 //     go through LDS to every lane (the LDS accesses of one wave complete in
-//     order), L(i,k) = a(i,k) / sqrt(d_k) and a(i,j) -= L(i,k) L(j,k).  The
-//     16 diagonal entries are also carried as uniform values updated by the
-//     same operations as their owners' (so bit-identical), which lets the
-//     next pivot's reciprocal square root start before the next exchange;
+//     order): L(i,k) = a(i,k)/sqrt(d_k), a(i,j) -= L(i,k) L(j,k), with the
+//     next pivot's reciprocal square root overlapping the exchange;
 //   one barrier; then wave w > kb subtracts the panel's rank-16 product from
 //     its own block column (MFMA) while wave kb inverts its diagonal block
-//     (lane c: column c of L_kk^{-1} by forward substitution, no exchange);
-//   after the last panel the off-diagonal blocks of X follow one block
-//     diagonal at a time from X_ij = -X_ii sum_{k=j}^{i-1} L_ik X_kj (MFMA).
+//     (lane c: column c of L_kk^{-1} by forward substitution, no exchange)
+//     and forms the rest of block row kb of X from
+//     X_kj = -X_kk sum_{m=j}^{k-1} L_km X_mj (MFMA), which only needs blocks
+//     finished before the barrier.  The sums of the last block row are formed
+//     by the idle waves while the last diagonal block is inverted.
 // Padding beyond b is the identity, so L and X are the identity there; only
 // the ceil(b/16) panels that hold columns of G are factored.
 // ---------------------------------------------------------------------------
 struct __align__(16) FactorLds {
     double L[64 * LDT];  // working matrix, then L (zero above the diagonal)
     double X[64 * LDT];  // L^{-1} (zero above the diagonal)
-    double col[2][64];   // column exchange of the panel wave
+    double col[2][128];  // column exchange of the panel wave (two values per row)
     double d0[64];       // diagonal of G + sI (pivot certificate)
     double sinv[64];     // 1 / L(k,k)
 };
 
 // L <- G + sI (first b diagonal entries shifted), identity-padded; X <- 0
-// with identity diagonal blocks past the factored panels.
+// with identity diagonal blocks past the factored panels.  All loads of a
+// thread are issued before the first store.
 __device__ __forceinline__ void factor_init(const double* G, double shift, int b, int nkb,
                                             FactorLds& F) {
-    for (int t = threadIdx.x; t < 64 * 64; t += 256) {
-        const int i = t >> 6, j = t & 63;
-        double v = (i < b && j < b) ? G[t] : (i == j ? 1.0 : 0.0);
+    double gv[16];
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+        const int t = threadIdx.x + 256 * e, i = t >> 6, j = t & 63;
+        gv[e] = G[(i < b && j < b) ? t : 0];
+    }
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+        const int t = threadIdx.x + 256 * e, i = t >> 6, j = t & 63;
+        double v = (i < b && j < b) ? gv[e] : (i == j ? 1.0 : 0.0);
         if (i == j && i < b) v += shift;
         F.L[i * LDT + j] = v;
         F.X[i * LDT + j] = (i == j && i >= 16 * nkb) ? 1.0 : 0.0;
@@ -166,40 +174,68 @@ __device__ __forceinline__ void factor_init(const double* G, double shift, int b
     __syncthreads();
 }
 
+__device__ __forceinline__ int pivot_fails(double piv, double d0, double rel) {
+    return !(d0 > 0.0 && piv > rel * d0 && piv < INFINITY);
+}
+
 // Panel kb by its own wave.  Returns 1 if a pivot falls to <= rel * (its
-// value in G + sI) or is not finite.
+// value in G + sI) or is not finite.  Two chains run side by side: at pivot
+// k, columns k+1 and k+2 are updated first and published together (the
+// exchange brings column k+1 at the block's rows and the diagonal entry of
+// column k+2), and the pivot of step k+1 is formed from uniform values by
+// the same operation its owner applies (bit-identical), so its reciprocal
+// square root overlaps the exchange; the rest of the update follows.
 __device__ __forceinline__ int factor_panel(FactorLds& F, int kb, double rel) {
     const int i = threadIdx.x & 63;
     const int c0 = 16 * kb;
-    double a[16], dg[16], dd0[16];
+    double a[16], dd0[16];
 #pragma unroll
     for (int jj = 0; jj < 16; ++jj) {
         a[jj] = F.L[i * LDT + c0 + jj];
-        dg[jj] = F.L[(c0 + jj) * LDT + c0 + jj];
         dd0[jj] = F.d0[c0 + jj];
     }
-    int bad = 0;
+    double c[16];  // column kk at the block's rows jj > kk
+    double dn;     // diagonal entry of column kk+1 before step kk
+    double s;      // 1 / sqrt(pivot kk)
+    {
+        double2_t* cb = reinterpret_cast<double2_t*>(F.col[0]);
+        cb[i] = double2_t{a[0], a[1]};
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (int jj = 0; jj < 16; ++jj) c[jj] = F.col[0][2 * (c0 + jj)];
+        dn = F.col[0][2 * (c0 + 1) + 1];
+    }
+    int bad = pivot_fails(c[0], dd0[0], rel);
+    s = rsqrt_nr(fmax(c[0], 1e-300));
     double sv = 0.0;  // lane jj < 16 keeps 1/L(c0+jj, c0+jj)
 #pragma unroll
     for (int kk = 0; kk < 16; ++kk) {
-        const double piv = dg[kk];
-        bad |= !(dd0[kk] > 0.0 && piv > rel * dd0[kk] && piv < INFINITY);
-        const double sk = rsqrt_nr(fmax(piv, 1e-300));
-        sv = (i == kk) ? sk : sv;
-        double* cb = F.col[kk & 1];
-        cb[i] = a[kk];
-        __builtin_amdgcn_wave_barrier();
-        double c[16];
-#pragma unroll
-        for (int jj = kk + 1; jj < 16; ++jj) c[jj] = cb[c0 + jj];
-        const double li = a[kk] * sk;
-        const double t = li * sk;
+        sv = (i == kk) ? s : sv;
+        const double li = a[kk] * s;
+        const double t = li * s;
         a[kk] = li;
+        double cn[16], dnn = 0.0, s_next = 0.0;
+        if (kk < 15) {
+            a[kk + 1] = fma(-t, c[kk + 1], a[kk + 1]);
+            if (kk < 14) a[kk + 2] = fma(-t, c[kk + 2], a[kk + 2]);
+            double* cb = F.col[(kk + 1) & 1];
+            reinterpret_cast<double2_t*>(cb)[i] = double2_t{a[kk + 1], kk < 14 ? a[kk + 2] : 0.0};
+            __builtin_amdgcn_wave_barrier();
 #pragma unroll
-        for (int jj = kk + 1; jj < 16; ++jj) {
-            a[jj] = fma(-t, c[jj], a[jj]);
-            dg[jj] = fma(-((c[jj] * sk) * sk), c[jj], dg[jj]);
+            for (int jj = kk + 2; jj < 16; ++jj) cn[jj] = cb[2 * (c0 + jj)];
+            if (kk < 14) dnn = cb[2 * (c0 + kk + 2) + 1];
+            __builtin_amdgcn_sched_barrier(0);
+            // pivot kk+1 as its owner forms it
+            const double piv = fma(-((c[kk + 1] * s) * s), c[kk + 1], dn);
+            bad |= pivot_fails(piv, dd0[kk + 1], rel);
+            s_next = rsqrt_nr(fmax(piv, 1e-300));
         }
+#pragma unroll
+        for (int jj = kk + 3; jj < 16; ++jj) a[jj] = fma(-t, c[jj], a[jj]);
+#pragma unroll
+        for (int jj = kk + 2; jj < 16; ++jj) c[jj] = cn[jj];
+        dn = dnn;
+        s = s_next;
     }
 #pragma unroll
     for (int jj = 0; jj < 16; ++jj) F.L[i * LDT + c0 + jj] = (i >= c0 + jj) ? a[jj] : 0.0;
@@ -207,24 +243,35 @@ __device__ __forceinline__ int factor_panel(FactorLds& F, int kb, double rel) {
     return bad;
 }
 
-// Wave w > kb: block column w (rows 16w..63) -= L(:, panel kb) L(w rows, panel kb)^T.
+// Wave w > kb: block column w (rows 16w..63) -= L(:, panel kb) L(w rows,
+// panel kb)^T.  The (up to three) tiles are computed together, clamped
+// duplicates discarded.
 __device__ __forceinline__ void update_block_column(FactorLds& F, int kb, int w) {
     const int lane = threadIdx.x & 63, li = lane & 15, lg = lane >> 4;
     const int p0 = 16 * kb, c0 = 16 * w;
-    for (int ti = w; ti < 4; ++ti) {
-        double4_t acc = {0.0, 0.0, 0.0, 0.0};
+    double4_t acc[3];
 #pragma unroll
-        for (int k4 = 0; k4 < 16; k4 += 4) {
-            const double av = F.L[(16 * ti + li) * LDT + p0 + k4 + lg];
-            const double bv = F.L[(c0 + li) * LDT + p0 + k4 + lg];
-            acc = mfma_f64_16x16x4(av, bv, acc);
+    for (int t = 0; t < 3; ++t) acc[t] = double4_t{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int k4 = 0; k4 < 16; k4 += 4) {
+        const double bv = F.L[(c0 + li) * LDT + p0 + k4 + lg];
+#pragma unroll
+        for (int t = 0; t < 3; ++t) {
+            const int ti = min(w + t, 3);
+            acc[t] = mfma_f64_16x16x4(F.L[(16 * ti + li) * LDT + p0 + k4 + lg], bv, acc[t]);
         }
+    }
 #pragma unroll
-        for (int v = 0; v < 4; ++v) F.L[(16 * ti + mfma_row_f64(lg, v)) * LDT + c0 + li] -= acc[v];
+    for (int t = 0; t < 3; ++t) {
+        if (w + t < 4) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+                F.L[(16 * (w + t) + mfma_row_f64(lg, v)) * LDT + c0 + li] -= acc[t][v];
+        }
     }
 }
 
-// Wave kb: X_kk = L_kk^{-1}; lane c solves L_kk x = e_c.
+// X_kk = L_kk^{-1}; lane c solves L_kk x = e_c.
 __device__ __forceinline__ void invert_diag(FactorLds& F, int kb) {
     const int lane = threadIdx.x & 63, c = lane & 15;
     const int c0 = 16 * kb;
@@ -248,71 +295,87 @@ __device__ __forceinline__ void invert_diag(FactorLds& F, int kb) {
     }
 }
 
-// Off-diagonal blocks of X, block diagonal lev = 1, 2, 3 in turn; wave w
-// computes X(w+lev, w).  Ends with a barrier.
-__device__ __forceinline__ void invert_offdiag(FactorLds& F, int nkb) {
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, li = lane & 15, lg = lane >> 4;
-    for (int lev = 1; lev < nkb; ++lev) {
-        __syncthreads();
-        const int j = w, i = w + lev;
-        if (i < nkb) {
-            double4_t u = {0.0, 0.0, 0.0, 0.0};  // sum_k L_ik X_kj
-            for (int k = j; k < i; ++k) {
+// U = sum_{m=j}^{k-1} L_km X_mj (one wave; accumulator layout).
+__device__ __forceinline__ double4_t xblock_sum(const FactorLds& F, int k, int j) {
+    const int lane = threadIdx.x & 63, li = lane & 15, lg = lane >> 4;
+    double4_t u = {0.0, 0.0, 0.0, 0.0};
+    for (int m = j; m < k; ++m) {
 #pragma unroll
-                for (int k4 = 0; k4 < 16; k4 += 4) {
-                    const double av = F.L[(16 * i + li) * LDT + 16 * k + k4 + lg];
-                    const double bv = F.X[(16 * k + k4 + lg) * LDT + 16 * j + li];
-                    u = mfma_f64_16x16x4(av, bv, u);
-                }
-            }
-            // U goes to the block's own place, then X_ij = -X_ii U
-            double* xij = F.X + 16 * i * LDT + 16 * j;
-#pragma unroll
-            for (int v = 0; v < 4; ++v) xij[mfma_row_f64(lg, v) * LDT + li] = u[v];
-            __builtin_amdgcn_wave_barrier();
-            double4_t x = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-            for (int k4 = 0; k4 < 16; k4 += 4) {
-                const double av = F.X[(16 * i + li) * LDT + 16 * i + k4 + lg];
-                const double bv = xij[(k4 + lg) * LDT + li];
-                x = mfma_f64_16x16x4(av, bv, x);
-            }
-            __builtin_amdgcn_wave_barrier();
-#pragma unroll
-            for (int v = 0; v < 4; ++v) xij[mfma_row_f64(lg, v) * LDT + li] = -x[v];
+        for (int k4 = 0; k4 < 16; k4 += 4) {
+            const double av = F.L[(16 * k + li) * LDT + 16 * m + k4 + lg];
+            const double bv = F.X[(16 * m + k4 + lg) * LDT + 16 * j + li];
+            u = mfma_f64_16x16x4(av, bv, u);
         }
     }
-    __syncthreads();
+    return u;
+}
+// X_kj = -X_kk U, with U passed through the block's own place in X.
+__device__ __forceinline__ void xblock_finish(FactorLds& F, int k, int j, double4_t u) {
+    const int lane = threadIdx.x & 63, li = lane & 15, lg = lane >> 4;
+    double* xkj = F.X + 16 * k * LDT + 16 * j;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) xkj[mfma_row_f64(lg, v) * LDT + li] = u[v];
+    __builtin_amdgcn_wave_barrier();
+    double4_t x = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int k4 = 0; k4 < 16; k4 += 4) {
+        const double av = F.X[(16 * k + li) * LDT + 16 * k + k4 + lg];
+        const double bv = xkj[(k4 + lg) * LDT + li];
+        x = mfma_f64_16x16x4(av, bv, x);
+    }
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int v = 0; v < 4; ++v) xkj[mfma_row_f64(lg, v) * LDT + li] = -x[v];
 }
 
 // Returns 1 (block-wide) if the certificate or the factorization fails.
 __device__ int chol_factor(const double* G, double shift, double rel, int b, FactorLds& F) {
-    const int nkb = (b + 15) / 16;
+    const int nkb = (b + 15) / 16, last = nkb - 1;
     factor_init(G, shift, b, nkb, F);
     const int w = threadIdx.x >> 6;
     int bad = 0;
     for (int kb = 0; kb < nkb; ++kb) {
         if (w == kb) bad |= factor_panel(F, kb, rel);
         __syncthreads();
-        if (w == kb)
+        if (w == kb) {
             invert_diag(F, kb);
-        else if (w > kb)
+            if (kb < last)
+                for (int j = kb - 1; j >= 0; --j) xblock_finish(F, kb, j, xblock_sum(F, kb, j));
+        } else if (w > kb) {
             update_block_column(F, kb, w);
+        }
     }
-    invert_offdiag(F, nkb);
+    // last block row: sums by the waves left of it, then X_last,j = -X_last,last U_j
+    double4_t u = {0.0, 0.0, 0.0, 0.0};
+    if (w < last) u = xblock_sum(F, last, w);
+    __syncthreads();
+    if (w < last) xblock_finish(F, last, w, u);
     return __syncthreads_or(bad);
 }
 
-// Sum of the P partial Grams in the order p = 0..P-1.  Pass 3 runs only on
-// the shifted route.
+// Sum of the P partial Grams: 64 workgroups of 64 entries; wave g sums the
+// partials p in [g P/4, (g+1) P/4) in order (all loads issued together, 16
+// at a time), and the four group sums are added in the order g = 0..3.
+// Pass 3 runs only on the shifted route.
 __global__ void __launch_bounds__(256) cq_reduce_kernel(CqDev q, int pass) {
     if (q.flags[0]) return;
     if (pass == 3 && !q.flags[1]) return;
-    const int e = blockIdx.x * 256 + threadIdx.x;
+    __shared__ double part[4][64];
+    const int lane = threadIdx.x & 63, g = threadIdx.x >> 6;
+    const int e = blockIdx.x * 64 + lane;
+    const int p0 = (g * q.P) / 4, p1 = ((g + 1) * q.P) / 4;
     double s = 0.0;
-#pragma unroll 8
-    for (int p = 0; p < q.P; ++p) s += q.gpart[(size_t)p * 4096 + e];
-    q.g[e] = s;
+    for (int p = p0; p < p1; p += 16) {
+        double v[16];
+#pragma unroll
+        for (int t = 0; t < 16; ++t) v[t] = q.gpart[(size_t)min(p + t, p1 - 1) * 4096 + e];
+#pragma unroll
+        for (int t = 0; t < 16; ++t)
+            if (p + t < p1) s += v[t];
+    }
+    part[g][lane] = s;
+    __syncthreads();
+    if (g == 0) q.g[e] = ((part[0][lane] + part[1][lane]) + part[2][lane]) + part[3][lane];
 }
 
 // Pass p (1..3): factor the pass's Gram (pass 1 with the certificate and,
@@ -356,12 +419,20 @@ __global__ void __launch_bounds__(256) cq_apply_kernel(CqDev q, int pass) {
         if (tid == 0 && bad) q.flags[0] = 1;
         if (tid == 0 && pass == 1) q.flags[1] = shifted ? 1 : 0;
         double* rf = q.rfac + (size_t)(pass - 1) * 4096;  // R(j, i) = L(i, j)
-        for (int t = tid; t < 64 * 64; t += 256) {
-            const int j = t >> 6, i = t & 63;
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+            const int t = tid + 256 * e, j = t >> 6, i = t & 63;
             rf[t] = (i >= j) ? F.L[i * LDT + j] : 0.0;
         }
     }
     if (bad) return;  // block-uniform; the panel stays as it was
+    // R^{-1} = X^T, row-major into the space of L (which is no longer needed)
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+        const int t = tid + 256 * e, k = t >> 6, c = t & 63;
+        F.L[k * LDT + c] = F.X[c * LDT + k];
+    }
 
     const bool final_pass = (pass == 3) || (pass == 2 && !shifted);
     const bool gram = !final_pass;
@@ -377,16 +448,20 @@ __global__ void __launch_bounds__(256) cq_apply_kernel(CqDev q, int pass) {
         __syncthreads();
         store_regs(T, v, r, r1, b);
         __syncthreads();
-        // R^{-1}(k, c) = X(c, k)
         double4_t acc[4];
 #pragma unroll
         for (int nb = 0; nb < 4; ++nb) acc[nb] = double4_t{0, 0, 0, 0};
-#pragma unroll 4
-        for (int kk = 0; kk < 64; kk += 4) {
-            const double av = T[(w * 16 + li) * LDT + kk + lg];
+        // R^{-1} is upper triangular: column block nb only needs k < 16 (nb + 1)
 #pragma unroll
-            for (int nb = 0; nb < 4; ++nb)
-                acc[nb] = mfma_f64_16x16x4(av, F.X[(nb * 16 + li) * LDT + kk + lg], acc[nb]);
+        for (int kb4 = 0; kb4 < 4; ++kb4) {
+#pragma unroll 2
+            for (int k4 = 0; k4 < 16; k4 += 4) {
+                const int kk = 16 * kb4 + k4;
+                const double av = T[(w * 16 + li) * LDT + kk + lg];
+#pragma unroll
+                for (int nb = kb4; nb < 4; ++nb)
+                    acc[nb] = mfma_f64_16x16x4(av, F.L[(kk + lg) * LDT + nb * 16 + li], acc[nb]);
+            }
         }
         __syncthreads();
 #pragma unroll
@@ -475,7 +550,7 @@ void launch_cq(double* a, int m, int b, int lda, double* r_out, double* ws, int*
     hipLaunchKernelGGL(cq_gram_kernel, dim3(q.P), dim3(256), 0, s, q);
     TTR_CHECK_LAUNCH();
     for (int pass = 1; pass <= 3; ++pass) {
-        hipLaunchKernelGGL(cq_reduce_kernel, dim3(16), dim3(256), 0, s, q, pass);
+        hipLaunchKernelGGL(cq_reduce_kernel, dim3(64), dim3(256), 0, s, q, pass);
         TTR_CHECK_LAUNCH();
         hipLaunchKernelGGL(cq_apply_kernel, dim3(q.P), dim3(256), 0, s, q, pass);
         TTR_CHECK_LAUNCH();
