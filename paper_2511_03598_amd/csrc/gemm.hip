@@ -4,12 +4,15 @@
 // M_k H(X_{k+1}) and the recompression products.
 //
 // 64x64 output tile per 256-thread workgroup, K staged through LDS in
-// 32-deep double-buffered slabs (eight loads per operand and thread in
-// flight per slab), each wave owning a 32x32 quadrant
+// 32-deep double-buffered slabs with two more slabs in flight in registers
+// (eight loads per operand and thread per slab), each wave owning a 32x32
+// quadrant
 // (2x2 MFMA blocks).  Operands are addressed by element strides so one
 // kernel serves every transpose; the global->LDS thread mapping follows the
 // contiguous dimension so loads stay coalesced.  Split-K writes partial
 // tiles that a second kernel sums in a fixed order (deterministic).
+#include <type_traits>
+
 #include "kernels.hpp"
 
 namespace ttr {
@@ -170,16 +173,20 @@ __global__ void __launch_bounds__(256) gemm_kernel(GemmArgs g, int kchunk, doubl
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = double4_t{0, 0, 0, 0};
 
-    Tile t;
+    // Three-stage pipeline: while slab k is multiplied from LDS, slab k+1
+    // waits in registers (ta) and slab k+2 is being loaded (tb), so each
+    // slab's global loads have two slabs of MFMA work to arrive.
+    Tile ta, tb;
     int buf = 0;
     if (kbeg < kend) {
-        load_tiles(g, m0, n0, kbeg, kend, t);
-        store_tiles(g, t, As[0], Bs[0]);
+        load_tiles(g, m0, n0, kbeg, kend, ta);
+        store_tiles(g, ta, As[0], Bs[0]);
+        if (kbeg + BK < kend) load_tiles(g, m0, n0, kbeg + BK, kend, ta);
     }
     __syncthreads();
     for (int k0 = kbeg; k0 < kend; k0 += BK) {
         const bool more = k0 + BK < kend;
-        if (more) load_tiles(g, m0, n0, k0 + BK, kend, t);
+        if (k0 + 2 * BK < kend) load_tiles(g, m0, n0, k0 + 2 * BK, kend, tb);
 #pragma unroll
         for (int s = 0; s < BK / 4; ++s) {
             const int kk = 4 * s + lg;
@@ -193,9 +200,10 @@ __global__ void __launch_bounds__(256) gemm_kernel(GemmArgs g, int kchunk, doubl
 #pragma unroll
                 for (int j = 0; j < 2; ++j) acc[i][j] = mfma_f64_16x16x4(av[i], bv[j], acc[i][j]);
         }
-        if (more) store_tiles(g, t, As[buf ^ 1], Bs[buf ^ 1]);
+        if (more) store_tiles(g, ta, As[buf ^ 1], Bs[buf ^ 1]);
         __syncthreads();
         buf ^= 1;
+        ta = tb;
     }
     const bool split = gridDim.z > 1;
 #pragma unroll
@@ -235,10 +243,156 @@ __global__ void __launch_bounds__(256) gemm_reduce_kernel(GemmArgs g, int splits
     *c = val;
 }
 
+// ---------------------------------------------------------------------------
+// Direct-operand kernel for K <= 256: a 32x32 output tile per 256-thread
+// workgroup; wave w multiplies its quarter of the K range for the whole tile
+// (2x2 MFMA blocks), loading its operands from global memory straight into
+// MFMA operand layout, all before the first MFMA (no LDS staging, no
+// barrier); the four partial tiles are added in LDS in wave order.  With
+// f64 MFMA issue as the bound, four waves per 32x32 tile finish a K = 200
+// product about four times sooner than one 64x64 tile per workgroup, and the
+// grid has four times as many workgroups.
+// ---------------------------------------------------------------------------
+constexpr int DKW = 16;  // k-steps of 4 per wave (K <= 256)
+
+// B's storage for the direct kernel: FP64, FP32 or bfloat16 (BT = 0, 1, 2),
+// with per-column exponents 2^bexp[n] (EXP) and slices summed in slice order
+// in the storage's arithmetic type (MS), as in load_b.  Compile-time choices
+// keep every operand load unconditional, so they are all issued together.
+template <int BT>
+struct BStore;
+template <>
+struct BStore<0> {
+    typedef double T;
+    static __device__ __forceinline__ const double* ptr(const GemmArgs& g) { return g.B; }
+};
+template <>
+struct BStore<1> {
+    typedef float T;
+    static __device__ __forceinline__ const float* ptr(const GemmArgs& g) { return g.Bf; }
+};
+template <>
+struct BStore<2> {
+    typedef unsigned short T;
+    static __device__ __forceinline__ const unsigned short* ptr(const GemmArgs& g) { return g.Bh; }
+};
+__device__ __forceinline__ double stored_f64(const double* p, size_t i) { return p[i]; }
+__device__ __forceinline__ float stored_f64(const float* p, size_t i) { return p[i]; }
+__device__ __forceinline__ float stored_f64(const unsigned short* p, size_t i) { return stored_f32(p, i); }
+
+template <int BT, bool EXP, bool MS>
+__global__ void __launch_bounds__(256) gemm_direct_kernel(GemmArgs g) {
+    typedef typename BStore<BT>::T ST;
+    typedef typename std::conditional<BT == 0, double, float>::type AT;  // B's arithmetic type
+    __shared__ double red[4][32][33];
+    const int m0 = blockIdx.x * 32, n0 = blockIdx.y * 32;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int li = lane & 15, lg = lane >> 4;
+    const int nks = (g.K + 3) / 4;
+    const int ks0 = (w * nks) / 4, ks1 = ((w + 1) * nks) / 4;
+    const ST* Bp = BStore<BT>::ptr(g);
+    // operands: A(m0 + 16 i + li, k), B(k, n0 + 16 j + li), k = 4 ks + lg
+    int rows[2], cols[2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        rows[i] = min(m0 + 16 * i + li, g.M - 1);
+        cols[i] = min(n0 + 16 * i + li, g.N - 1);
+    }
+    int bex[2] = {0, 0};
+    if (EXP) {
+#pragma unroll
+        for (int i = 0; i < 2; ++i) bex[i] = g.bexp[cols[i]];
+    }
+    double av[DKW][2];
+    AT bs[DKW][2];
+#pragma unroll
+    for (int t = 0; t < DKW; ++t) {
+        const int kc = min(4 * (ks0 + t) + lg, g.K - 1);
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            av[t][i] = g.A[(size_t)rows[i] * g.sam + (size_t)kc * g.sak];
+            bs[t][i] = stored_f64(Bp, (size_t)kc * g.sbk + (size_t)cols[i] * g.sbn);
+        }
+    }
+    if (MS) {
+        for (int sl = 1; sl < g.bslices; ++sl) {
+            const ST* Bs = Bp + (size_t)sl * g.bstride;
+#pragma unroll
+            for (int t = 0; t < DKW; ++t) {
+                const int kc = min(4 * (ks0 + t) + lg, g.K - 1);
+#pragma unroll
+                for (int i = 0; i < 2; ++i) bs[t][i] += stored_f64(Bs, (size_t)kc * g.sbk + (size_t)cols[i] * g.sbn);
+            }
+        }
+    }
+    double4_t acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = double4_t{0, 0, 0, 0};
+#pragma unroll
+    for (int t = 0; t < DKW; ++t) {
+        const int ks = ks0 + t;
+        if (ks < ks1) {  // uniform per wave
+            // k beyond K: the clamped operands are finite copies; zero A's
+            const bool kok = 4 * ks + lg < g.K;
+            const double a0 = kok ? av[t][0] : 0.0, a1 = kok ? av[t][1] : 0.0;
+            double b0 = (double)bs[t][0], b1 = (double)bs[t][1];
+            if (EXP) {
+                b0 = ldexp(b0, bex[0]);
+                b1 = ldexp(b1, bex[1]);
+            }
+            acc[0][0] = mfma_f64_16x16x4(a0, b0, acc[0][0]);
+            acc[0][1] = mfma_f64_16x16x4(a0, b1, acc[0][1]);
+            acc[1][0] = mfma_f64_16x16x4(a1, b0, acc[1][0]);
+            acc[1][1] = mfma_f64_16x16x4(a1, b1, acc[1][1]);
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) red[w][16 * i + mfma_row_f64(lg, v)][16 * j + li] = acc[i][j][v];
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const int idx = threadIdx.x + 256 * e, r = idx >> 5, c = idx & 31;
+        const int row = m0 + r, col = n0 + c;
+        if (row < g.M && col < g.N) {
+            const double sum = ((red[0][r][c] + red[1][r][c]) + red[2][r][c]) + red[3][r][c];
+            double* cp = g.C + c_offset(g, row, col);
+            double val = g.alpha * sum;
+            if (g.beta != 0.0) val += g.beta * (*cp);
+            *cp = val;
+        }
+    }
+}
+
+template <int BT, bool EXP>
+void launch_direct(const GemmArgs& g, dim3 grid, hipStream_t s) {
+    if (g.bslices > 1)
+        hipLaunchKernelGGL((gemm_direct_kernel<BT, EXP, true>), grid, dim3(256), 0, s, g);
+    else
+        hipLaunchKernelGGL((gemm_direct_kernel<BT, EXP, false>), grid, dim3(256), 0, s, g);
+}
+
 }  // namespace
 
 void launch_gemm(const GemmArgs& g, int splits, double* partials, hipStream_t s) {
     if (g.M <= 0 || g.N <= 0) return;
+    if (g.K >= 1 && g.K <= 4 * 4 * DKW) {
+        dim3 grid(ceil_div(g.M, 32), ceil_div(g.N, 32));
+        const bool ex = g.bexp != nullptr;
+        if (g.Bf)
+            ex ? launch_direct<1, true>(g, grid, s) : launch_direct<1, false>(g, grid, s);
+        else if (g.Bh)
+            ex ? launch_direct<2, true>(g, grid, s) : launch_direct<2, false>(g, grid, s);
+        else
+            launch_direct<0, false>(g, grid, s);
+        TTR_CHECK_LAUNCH();
+        return;
+    }
     if (g.K <= 0) splits = 1;
     if (splits < 1) splits = 1;
     int kchunk = g.K;
