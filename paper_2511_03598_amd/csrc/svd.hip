@@ -2,10 +2,11 @@
 // right-to-left truncation pass of Remark 2 (the "tau or l_k truncated SVD"
 // of the TT-Rounding algorithm, Sec. 2.2, applied to R^T from the LQ of
 // H(Y_k)).  Columns of A are rotated pairwise until mutually orthogonal:
-// A V = U Sigma.  Pairs follow a round-robin tournament, q/2 disjoint pairs
-// per round, each pair owned by a 16-lane group that holds its two columns
-// (4 rows per lane) in registers for the round (DPP reductions); one
-// barrier per round.
+// A V = U Sigma.  Pairs follow a recursive bipartite order: in each phase
+// every 16-lane group keeps one column of A and V in registers (4 rows per
+// lane) and meets a sequence of moving columns, one per round (DPP
+// reductions, one barrier per round), so a round moves only half of the
+// columns through LDS.
 // One-sided Jacobi gives singular values to high relative accuracy, which
 // the tolerance-based truncation needs.
 #include <algorithm>
@@ -87,63 +88,72 @@ __global__ void __launch_bounds__(512) svd_jacobi_kernel(const double* A, int ld
     int sexp = 0;
     if (amax > 0.0 && amax < INFINITY) (void)frexp(amax, &sexp);
     for (int t = tid; t < 64 * LD; t += 512) As[t] = ldexp(As[t], -sexp);
-    const int qq = q + (q & 1);
     // Rotate while (x.y)^2 > tol^2 (x.x)(y.y); tol sits well above the
     // rounding error of a p-term dot product (~p u) so the sweep test can be met.
     const double tol2 = 1e-26;
     if (tid == 0) nsweeps = 0;
     // One column pair per 16-lane group; lane l16 holds rows l16, l16+16, ...
     const int g8 = tid >> 4, l8 = tid & 15;
-    const bool has_pair = g8 < qq / 2 && qq >= 2;
     __syncthreads();
-    for (int sweep = 0; sweep < 60 && qq >= 2; ++sweep) {
+    for (int sweep = 0; sweep < 60 && q >= 2; ++sweep) {
         if (tid == 0) rotated = 0;
         __syncthreads();
-        // Round-robin positions g8 and qq-1-g8; players rotate by one per round.
-        int v1 = g8 - 1, v2 = qq - 2 - g8;  // (pos - 1) for the two positions
-        for (int r = 0; r < qq - 1; ++r) {
-            int i1 = -1, i2 = -1;
-            if (has_pair) {
-                i1 = (g8 == 0) ? 0 : 1 + v1;
-                i2 = 1 + v2;
-                if (i1 > i2) {
-                    const int tmp = i1;
-                    i1 = i2;
-                    i2 = tmp;
-                }
-                if (i2 >= q) i1 = -1;  // bye
+        // Recursive bipartite order on 64 column slots (columns >= q are
+        // absent): phase p splits the slots into 2^p blocks of 64 >> p; group
+        // g keeps column f = lo + j of its block's first half in registers
+        // for the whole phase and meets the second half's columns one per
+        // round, so only the moving column passes through LDS each round.
+        // Every pair meets once per sweep (63 rounds of up to 32 pairs).
+        for (int p = 0; p < 6; ++p) {
+            const int h1 = 32 >> p, j = g8 & (h1 - 1), lo = (g8 >> (5 - p)) * 2 * h1;
+            const int f = lo + j;
+            double x[4], vx[4];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                x[t] = As[min(f, 63) * LD + l8 + 16 * t];
+                vx[t] = V[min(f, 63) * LD + l8 + 16 * t];
             }
-            if (++v1 >= qq - 1) v1 -= qq - 1;
-            if (++v2 >= qq - 1) v2 -= qq - 1;
-            if (i1 >= 0) {
-                double x[4], y[4], vx[4], vy[4];
-                double al = 0.0, be = 0.0, ga = 0.0;
+            bool fdirty = false;
+            for (int r = 0; r < h1; ++r) {
+                const int m = lo + h1 + ((j + r) & (h1 - 1));
+                if (f < q && m < q) {  // uniform per group
+                    double y[4];
+                    double al = 0.0, be = 0.0, ga = 0.0;
 #pragma unroll
-                for (int t = 0; t < 4; ++t) {
-                    x[t] = As[i1 * LD + l8 + 16 * t];
-                    y[t] = As[i2 * LD + l8 + 16 * t];
-                    vx[t] = V[i1 * LD + l8 + 16 * t];
-                    vy[t] = V[i2 * LD + l8 + 16 * t];
-                }
+                    for (int t = 0; t < 4; ++t) y[t] = As[m * LD + l8 + 16 * t];
 #pragma unroll
-                for (int t = 0; t < 4; ++t) {
-                    al += x[t] * x[t];
-                    be += y[t] * y[t];
-                    ga += x[t] * y[t];
-                }
-                group16_sum3(al, be, ga);
-                if (ga * ga > tol2 * (al * be)) {
-                    if (l8 == 0) rotated = 1;
-                    double c, sn;
-                    jacobi_cs(al, be, ga, c, sn);
-#pragma unroll
-                    for (int k = 0; k < 4; ++k) {
-                        const int i = l8 + 16 * k;
-                        As[i1 * LD + i] = c * x[k] - sn * y[k];
-                        As[i2 * LD + i] = sn * x[k] + c * y[k];
-                        V[i1 * LD + i] = c * vx[k] - sn * vy[k];
-                        V[i2 * LD + i] = sn * vx[k] + c * vy[k];
+                    for (int t = 0; t < 4; ++t) {
+                        al += x[t] * x[t];
+                        be += y[t] * y[t];
+                        ga += x[t] * y[t];
                     }
+                    group16_sum3(al, be, ga);
+                    if (ga * ga > tol2 * (al * be)) {
+                        if (l8 == 0) rotated = 1;
+                        fdirty = true;
+                        double vy[4];
+#pragma unroll
+                        for (int t = 0; t < 4; ++t) vy[t] = V[m * LD + l8 + 16 * t];
+                        double c, sn;
+                        jacobi_cs(al, be, ga, c, sn);
+#pragma unroll
+                        for (int k = 0; k < 4; ++k) {
+                            const int i = l8 + 16 * k;
+                            const double xk = x[k], yk = y[k], uk = vx[k], wk = vy[k];
+                            x[k] = c * xk - sn * yk;
+                            vx[k] = c * uk - sn * wk;
+                            As[m * LD + i] = sn * xk + c * yk;
+                            V[m * LD + i] = sn * uk + c * wk;
+                        }
+                    }
+                }
+                __syncthreads();
+            }
+            if (fdirty) {
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    As[f * LD + l8 + 16 * t] = x[t];
+                    V[f * LD + l8 + 16 * t] = vx[t];
                 }
             }
             __syncthreads();
