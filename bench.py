@@ -100,11 +100,12 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-parity", action="store_true")
-    ap.add_argument("--workload", choices=["c2", "c4", "c5", "sum"], default="c2",
+    ap.add_argument("--workload", choices=["c2", "c4", "c5", "sum", "precision"], default="c2",
                     help="c2 (default): the fixed-rank rounding the metric is quoted on; "
                          "c4: batched adaptive rounding vs a plain loop; c5: served rounding "
                          "under Poisson arrivals (p50/p99 latency); sum: one large C5 request "
-                         "rounded term by term vs the assembled formal sum")
+                         "rounded term by term vs the assembled formal sum; precision: adaptive "
+                         "rounding of C3 with FP64/FP32/BF16 sketches at tol 1e-4..1e-10")
     ap.add_argument("--count", type=int, default=256, help="c4: tensors in the batch")
     ap.add_argument("--requests", type=int, default=120, help="c5: requests per arrival rate")
     ap.add_argument("--workers", type=int, default=8, help="c4/c5: concurrent roundings")
@@ -126,6 +127,8 @@ def main():
         return run_c5(args)
     if args.workload == "sum":
         return run_sum(args)
+    if args.workload == "precision":
+        return run_precision(args)
     if args.copy_calibration:
         src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")  # 1 GiB
         dst = torch.empty_like(src)
@@ -329,6 +332,66 @@ def run_sum(args):
         "same_ranks": res["sum"][1]["ranks"] == res["formal"][1]["ranks"],
         "max_entry_diff_sum_vs_formal": entry_diff, "entries_sampled": int(idx.shape[0]),
         "timing": timing,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def run_precision(args):
+    """Adaptive rounding of C3 (d=10, n=256, base ranks 200 with bond
+    spectra 10^-(j-1)/8, plus a noise TT of ranks 100; formal ranks 300) with
+    the sketch (W) kept in FP64, FP32 or BF16, at tol 1e-4 .. 1e-10 (ell
+    blocks of 16): rate, ranks, range-finder iterations, regeneration passes
+    and partial-contraction time per precision.  The error against X is
+    measured on a reduced C3 (d=6, n=64, ranks 100 + 50) with the oracle's
+    TT norms.  The estimator and the sweep run in FP64 from S = V(Y_k) W, so
+    a reduced-precision W only perturbs the test matrix; whether it ever
+    stalls the adaptive loop is what this run checks."""
+    import torch
+
+    import paper_2511_03598_amd as ttr
+    import ttgen
+    from oracle import tt as ott
+
+    tols = (1e-4, 1e-6, 1e-8, 1e-10)
+    precs = ("f64", "f32", "bf16")
+    big = [torch.tensor(c, device="cuda") for c in ttgen.c3()]
+    small_h = ttgen.c3(d=6, n=64, r=100, noise_r=50)
+    small = [torch.tensor(c, device="cuda") for c in small_h]
+    rows = []
+    for tol in tols:
+        for prec in precs:
+            for _ in range(max(1, args.warmup)):
+                ttr.round_adaptive(big, tol, 16, 42, prec=prec)
+            torch.cuda.synchronize()
+            ttr.kernel_timing(True)
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                y, info = ttr.round_adaptive(big, tol, 16, 42, prec=prec)
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t0) / args.steps
+            ttr.kernel_timing(False)
+            pc_ms = ttr.kernel_timing_read("partial_contraction")[1] / args.steps
+            ys, infos = ttr.round_adaptive(small, tol, 16, 42, prec=prec)
+            err = float(ott.rel_err(small_h, [c.cpu().numpy() for c in ys]))
+            rows.append({"tol": tol, "prec": prec, "roundings_per_s": 1.0 / dt,
+                         "ranks": info["ranks"], "iterations": info["iterations"],
+                         "passes": info["passes"], "partial_contraction_ms": pc_ms,
+                         "reduced_c3_ranks": infos["ranks"], "reduced_c3_rel_err": err})
+            print(json.dumps(rows[-1]), file=sys.stderr, flush=True)
+    same = all(r["ranks"] == next(q["ranks"] for q in rows if q["tol"] == r["tol"] and q["prec"] == "f64")
+               and r["iterations"] == next(q["iterations"] for q in rows
+                                           if q["tol"] == r["tol"] and q["prec"] == "f64")
+               for r in rows)
+    within = all(r["reduced_c3_rel_err"] <= r["tol"] for r in rows)
+    bf = next(r for r in rows if r["tol"] == 1e-8 and r["prec"] == "bf16")
+    out = {
+        "metric": "adaptive TT-roundings/s (C3, BF16 sketch, tol 1e-8)", "value": bf["roundings_per_s"],
+        "unit": "TT-roundings/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "higher_is_better": True, "data": "synthetic", "dtype": "bf16/f32/f64 sketch, f64 sweep",
+        "config": {"workload": "C3: d=10 n=256 base ranks 200 (spectra 10^-(j-1)/8) + noise TT ranks "
+                               "100 (sigma 1e-6), formal ranks 300; adaptive, ell blocks of 16"},
+        "same_ranks_and_iterations_all_precisions": same, "errors_within_tol": within,
+        "rows": rows,
     }
     print(json.dumps(out), flush=True)
 

@@ -165,3 +165,26 @@ def test_errors_from_device_calls(lib):
         lib.round_fixed(x, 0, 1)
     with pytest.raises(lib.TTError):
         lib.round_adaptive(x, -1.0, 4, 1)
+
+
+@pytest.mark.parametrize("tol", [1e-6, 1e-9])
+def test_adaptive_sketch_precision_does_not_floor(lib, tol):
+    """The range finder and its estimator run in FP64 on S = V(Y_k) W, so an
+    FP32 or bfloat16 W only perturbs the test matrix: on a C3-shaped input
+    (orthonormal cores with bond spectra 10^-(j-1)/8 plus a noise TT) the
+    three sketch precisions choose the same ranks with the same number of
+    range-finder iterations, truncating well below the formal ranks, and all
+    meet the tolerance."""
+    x = ttgen.c3(d=6, n=48, r=120, noise_r=20)
+    xd = to_dev(x)
+    ref = None
+    for prec in ("f64", "f32", "bf16"):
+        y, info = lib.round_adaptive(xd, tol, 8, 42, prec=prec)
+        err = tt.rel_err(x, to_host(y))
+        say("precision", tol, prec, info["ranks"], info["iterations"], err)
+        assert err <= tol
+        assert max(info["ranks"]) < 120
+        if ref is None:
+            ref = info
+        assert info["ranks"] == ref["ranks"]
+        assert info["iterations"] == ref["iterations"]
