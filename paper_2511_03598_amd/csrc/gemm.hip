@@ -244,16 +244,18 @@ __global__ void __launch_bounds__(256) gemm_reduce_kernel(GemmArgs g, int splits
 }
 
 // ---------------------------------------------------------------------------
-// Direct-operand kernel for K <= 256: a 32x32 output tile per 256-thread
-// workgroup; wave w multiplies its quarter of the K range for the whole tile
-// (2x2 MFMA blocks), loading its operands from global memory straight into
-// MFMA operand layout, all before the first MFMA (no LDS staging, no
-// barrier); the four partial tiles are added in LDS in wave order.  With
+// Direct-operand kernel (K <= 256, or K <= 1024 on grids of >= 64 tiles): a
+// 32x32 output tile per 256-thread workgroup; K is taken in chunks of up to
+// 256, and within a chunk wave w multiplies its quarter of the k range for
+// the whole tile (2x2 MFMA blocks), loading its operands from global memory
+// straight into MFMA operand layout, all before the chunk's first MFMA (no
+// LDS staging, no barrier); the four partial tiles are added in LDS in wave
+// order.  With
 // f64 MFMA issue as the bound, four waves per 32x32 tile finish a K = 200
 // product about four times sooner than one 64x64 tile per workgroup, and the
 // grid has four times as many workgroups.
 // ---------------------------------------------------------------------------
-constexpr int DKW = 16;  // k-steps of 4 per wave (K <= 256)
+constexpr int DKW_MAX = 16;  // k-steps of 4 per wave and chunk at most (chunks of 256)
 
 // B's storage for the direct kernel: FP64, FP32 or bfloat16 (BT = 0, 1, 2),
 // with per-column exponents 2^bexp[n] (EXP) and slices summed in slice order
@@ -280,7 +282,9 @@ __device__ __forceinline__ double stored_f64(const double* p, size_t i) { return
 __device__ __forceinline__ float stored_f64(const float* p, size_t i) { return p[i]; }
 __device__ __forceinline__ float stored_f64(const unsigned short* p, size_t i) { return stored_f32(p, i); }
 
-template <int BT, bool EXP, bool MS>
+// DKW: k-steps of 4 per wave the kernel loads (4, 8 or 16: K <= 16 DKW),
+// so short products do not issue loads they do not use.
+template <int BT, bool EXP, bool MS, int DKW>
 __global__ void __launch_bounds__(256) gemm_direct_kernel(GemmArgs g) {
     typedef typename BStore<BT>::T ST;
     typedef typename std::conditional<BT == 0, double, float>::type AT;  // B's arithmetic type
@@ -288,8 +292,6 @@ __global__ void __launch_bounds__(256) gemm_direct_kernel(GemmArgs g) {
     const int m0 = blockIdx.x * 32, n0 = blockIdx.y * 32;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int li = lane & 15, lg = lane >> 4;
-    const int nks = (g.K + 3) / 4;
-    const int ks0 = (w * nks) / 4, ks1 = ((w + 1) * nks) / 4;
     const ST* Bp = BStore<BT>::ptr(g);
     // operands: A(m0 + 16 i + li, k), B(k, n0 + 16 j + li), k = 4 ks + lg
     int rows[2], cols[2];
@@ -303,49 +305,56 @@ __global__ void __launch_bounds__(256) gemm_direct_kernel(GemmArgs g) {
 #pragma unroll
         for (int i = 0; i < 2; ++i) bex[i] = g.bexp[cols[i]];
     }
-    double av[DKW][2];
-    AT bs[DKW][2];
-#pragma unroll
-    for (int t = 0; t < DKW; ++t) {
-        const int kc = min(4 * (ks0 + t) + lg, g.K - 1);
-#pragma unroll
-        for (int i = 0; i < 2; ++i) {
-            av[t][i] = g.A[(size_t)rows[i] * g.sam + (size_t)kc * g.sak];
-            bs[t][i] = stored_f64(Bp, (size_t)kc * g.sbk + (size_t)cols[i] * g.sbn);
-        }
-    }
-    if (MS) {
-        for (int sl = 1; sl < g.bslices; ++sl) {
-            const ST* Bs = Bp + (size_t)sl * g.bstride;
-#pragma unroll
-            for (int t = 0; t < DKW; ++t) {
-                const int kc = min(4 * (ks0 + t) + lg, g.K - 1);
-#pragma unroll
-                for (int i = 0; i < 2; ++i) bs[t][i] += stored_f64(Bs, (size_t)kc * g.sbk + (size_t)cols[i] * g.sbn);
-            }
-        }
-    }
     double4_t acc[2][2];
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = double4_t{0, 0, 0, 0};
+    // K in chunks of 16 DKW; within a chunk wave w takes its quarter of the
+    // k-steps
+    for (int kb = 0; kb < g.K; kb += 16 * DKW) {
+        const int nks = (min(g.K - kb, 16 * DKW) + 3) / 4;
+        const int ks0 = (w * nks) / 4, ks1 = ((w + 1) * nks) / 4;
+        double av[DKW][2];
+        AT bs[DKW][2];
 #pragma unroll
-    for (int t = 0; t < DKW; ++t) {
-        const int ks = ks0 + t;
-        if (ks < ks1) {  // uniform per wave
-            // k beyond K: the clamped operands are finite copies; zero A's
-            const bool kok = 4 * ks + lg < g.K;
-            const double a0 = kok ? av[t][0] : 0.0, a1 = kok ? av[t][1] : 0.0;
-            double b0 = (double)bs[t][0], b1 = (double)bs[t][1];
-            if (EXP) {
-                b0 = ldexp(b0, bex[0]);
-                b1 = ldexp(b1, bex[1]);
+        for (int t = 0; t < DKW; ++t) {
+            const int kc = min(kb + 4 * (ks0 + t) + lg, g.K - 1);
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
+                av[t][i] = g.A[(size_t)rows[i] * g.sam + (size_t)kc * g.sak];
+                bs[t][i] = stored_f64(Bp, (size_t)kc * g.sbk + (size_t)cols[i] * g.sbn);
             }
-            acc[0][0] = mfma_f64_16x16x4(a0, b0, acc[0][0]);
-            acc[0][1] = mfma_f64_16x16x4(a0, b1, acc[0][1]);
-            acc[1][0] = mfma_f64_16x16x4(a1, b0, acc[1][0]);
-            acc[1][1] = mfma_f64_16x16x4(a1, b1, acc[1][1]);
+        }
+        if (MS) {
+            for (int sl = 1; sl < g.bslices; ++sl) {
+                const ST* Bs = Bp + (size_t)sl * g.bstride;
+#pragma unroll
+                for (int t = 0; t < DKW; ++t) {
+                    const int kc = min(kb + 4 * (ks0 + t) + lg, g.K - 1);
+#pragma unroll
+                    for (int i = 0; i < 2; ++i)
+                        bs[t][i] += stored_f64(Bs, (size_t)kc * g.sbk + (size_t)cols[i] * g.sbn);
+                }
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < DKW; ++t) {
+            const int ks = ks0 + t;
+            if (ks < ks1) {  // uniform per wave
+                // k beyond K: the clamped operands are finite copies; zero A's
+                const bool kok = kb + 4 * ks + lg < g.K;
+                const double a0 = kok ? av[t][0] : 0.0, a1 = kok ? av[t][1] : 0.0;
+                double b0 = (double)bs[t][0], b1 = (double)bs[t][1];
+                if (EXP) {
+                    b0 = ldexp(b0, bex[0]);
+                    b1 = ldexp(b1, bex[1]);
+                }
+                acc[0][0] = mfma_f64_16x16x4(a0, b0, acc[0][0]);
+                acc[0][1] = mfma_f64_16x16x4(a0, b1, acc[0][1]);
+                acc[1][0] = mfma_f64_16x16x4(a1, b0, acc[1][0]);
+                acc[1][1] = mfma_f64_16x16x4(a1, b1, acc[1][1]);
+            }
         }
     }
 #pragma unroll
@@ -369,19 +378,31 @@ __global__ void __launch_bounds__(256) gemm_direct_kernel(GemmArgs g) {
     }
 }
 
+template <int BT, bool EXP, int DKW>
+void launch_direct_k(const GemmArgs& g, dim3 grid, hipStream_t s) {
+    if (g.bslices > 1)
+        hipLaunchKernelGGL((gemm_direct_kernel<BT, EXP, true, DKW>), grid, dim3(256), 0, s, g);
+    else
+        hipLaunchKernelGGL((gemm_direct_kernel<BT, EXP, false, DKW>), grid, dim3(256), 0, s, g);
+}
 template <int BT, bool EXP>
 void launch_direct(const GemmArgs& g, dim3 grid, hipStream_t s) {
-    if (g.bslices > 1)
-        hipLaunchKernelGGL((gemm_direct_kernel<BT, EXP, true>), grid, dim3(256), 0, s, g);
+    const int per_wave = ceil_div(ceil_div(std::min(g.K, 16 * DKW_MAX), 4), 4);  // busiest wave's k-steps
+    if (per_wave <= 4)
+        launch_direct_k<BT, EXP, 4>(g, grid, s);
+    else if (per_wave <= 8)
+        launch_direct_k<BT, EXP, 8>(g, grid, s);
     else
-        hipLaunchKernelGGL((gemm_direct_kernel<BT, EXP, false>), grid, dim3(256), 0, s, g);
+        launch_direct_k<BT, EXP, 16>(g, grid, s);
 }
 
 }  // namespace
 
 void launch_gemm(const GemmArgs& g, int splits, double* partials, hipStream_t s) {
     if (g.M <= 0 || g.N <= 0) return;
-    if (g.K >= 1 && g.K <= 4 * 4 * DKW) {
+    // direct kernel: K <= 256, or K <= 1024 on a grid of at least 64 tiles
+    const int64_t dtiles = (int64_t)ceil_div(g.M, 32) * ceil_div(g.N, 32);
+    if (g.K >= 1 && (g.K <= 16 * DKW_MAX || (g.K <= 64 * DKW_MAX && dtiles >= 64))) {
         dim3 grid(ceil_div(g.M, 32), ceil_div(g.N, 32));
         const bool ex = g.bexp != nullptr;
         if (g.Bf)
