@@ -100,6 +100,9 @@ typedef struct {        /* diagnostics of the calling thread's last rounding */
     double min_margin;  /* min |est - tau| / tau over adaptive decisions     */
     int32_t passes;     /* partial-contraction passes (1 + regenerations)    */
     int32_t iterations; /* adaptive loop iterations (estimates computed)     */
+    int32_t qr_retries; /* 1 if the rounding was repeated because a CholeskyQR
+                           broke down while the Householder fallback was
+                           deferred (the result is that of the repeat)       */
 } tt_info;
 
 /* Output capacity (elements) per core: cap[k-1] = c_{k-1} n_k c_k with

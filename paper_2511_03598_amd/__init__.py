@@ -52,7 +52,7 @@ class _Opts(ctypes.Structure):
 class _Info(ctypes.Structure):
     _fields_ = [("tau", ctypes.c_double), ("nrmx", ctypes.c_double),
                 ("min_margin", ctypes.c_double), ("passes", ctypes.c_int32),
-                ("iterations", ctypes.c_int32)]
+                ("iterations", ctypes.c_int32), ("qr_retries", ctypes.c_int32)]
 
 
 class _ServerCfg(ctypes.Structure):
@@ -281,7 +281,7 @@ def last_info():
     i = _Info()
     _check(lib().tt_last_info(ctypes.byref(i)))
     return {"tau": i.tau, "nrmx": i.nrmx, "min_margin": i.min_margin, "passes": i.passes,
-            "iterations": i.iterations}
+            "iterations": i.iterations, "qr_retries": i.qr_retries}
 
 
 def gaussian_factor(seed, mode, n, col0, ncols, device="cuda", stream=None):

@@ -83,6 +83,7 @@ void store_info(const ttr::RoundInfo& i) {
     g_info.min_margin = i.min_margin;
     g_info.passes = i.passes;
     g_info.iterations = i.iterations;
+    g_info.qr_retries = i.qr_retries;
 }
 
 
@@ -92,6 +93,7 @@ void fill_info(tt_info& o, const ttr::RoundInfo& i) {
     o.min_margin = i.min_margin;
     o.passes = i.passes;
     o.iterations = i.iterations;
+    o.qr_retries = i.qr_retries;
 }
 
 int64_t out_capacity_total(const ttr::Shape& s, std::vector<int64_t>* per_core) {

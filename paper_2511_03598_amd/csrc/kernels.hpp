@@ -118,10 +118,12 @@ void launch_qr(const QrPlan& p, double* a, double* r_out, double* ws, int* count
 // CholeskyQR2 / shifted CholeskyQR3 fast path (qr_chol.hip), b <= 64,
 // m >= b.  flags[0] is set to 1 when a pass breaks down (rank-deficient
 // panel), in which case `a` is left untouched for the Householder path
-// (launch_qr with only_if=flags); flags[1] records the shifted route.
+// (launch_qr with only_if=flags); flags[1] records the shifted route.  A
+// non-null `sticky` is also set to 1 on a breakdown and never cleared, so
+// a caller can check many QRs at once.
 size_t cq_workspace_doubles(int m, int b);
 void launch_cq(double* a, int m, int b, int lda, double* r_out, double* ws, int* flags,
-               hipStream_t s);
+               hipStream_t s, int* sticky = nullptr);
 
 // ---- small SVD by one-sided Jacobi (svd.hip) -------------------------------
 // A (p x q, column-major, lda), p >= q, q <= 64.  On return: G (p x q,

@@ -42,6 +42,7 @@ struct CqDev {
     double* rfac;   // 3 x 64 x 64 R per pass (row-major, identity-padded)
     double* r_out;  // optional b x b column-major R of the panel
     int* flags;
+    int* sticky;    // optional: set to 1 as well when a pass breaks down
 };
 
 __device__ __forceinline__ void block_rows(const CqDev& q, int blk, int& r0, int& r1) {
@@ -416,7 +417,10 @@ __global__ void __launch_bounds__(256) cq_apply_kernel(CqDev q, int pass) {
     }
     const bool shifted = (pass == 1) ? (shift > 0.0) : shifted_in;
     if (blockIdx.x == 0) {
-        if (tid == 0 && bad) q.flags[0] = 1;
+        if (tid == 0 && bad) {
+            q.flags[0] = 1;
+            if (q.sticky) *q.sticky = 1;
+        }
         if (tid == 0 && pass == 1) q.flags[1] = shifted ? 1 : 0;
         double* rf = q.rfac + (size_t)(pass - 1) * 4096;  // R(j, i) = L(i, j)
 #pragma unroll
@@ -533,7 +537,7 @@ size_t cq_workspace_doubles(int m, int b) {
 }
 
 void launch_cq(double* a, int m, int b, int lda, double* r_out, double* ws, int* flags,
-               hipStream_t s) {
+               hipStream_t s, int* sticky) {
     CqDev q{};
     q.m = m;
     q.b = b;
@@ -547,6 +551,7 @@ void launch_cq(double* a, int m, int b, int lda, double* r_out, double* ws, int*
     q.rfac = q.g + 4096;
     q.r_out = r_out;
     q.flags = flags;
+    q.sticky = sticky;
     hipLaunchKernelGGL(cq_gram_kernel, dim3(q.P), dim3(256), 0, s, q);
     TTR_CHECK_LAUNCH();
     for (int pass = 1; pass <= 3; ++pass) {

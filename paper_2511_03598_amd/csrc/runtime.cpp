@@ -59,7 +59,13 @@ struct DevBuf {
 struct Workspace {
     int device = -1;
     DevBuf omega, w, colexp, maxexp, dn, doff, y0, y1, q, sbuf, tbuf, m, qrws, cqws, qrcnt, part, scal,
-        sumpart, sumcnt, small1, small2, small3, small4, tint, tmp;
+        sumpart, sumcnt, small1, small2, small3, small4, tint, tmp, qrsticky;
+    // Deferred Householder fallback: while a rounding runs with lazy_qr set,
+    // qr() launches only the CholeskyQR kernels and a breakdown sets the
+    // device int qr_sticky; scalar readbacks fetch it too (host_int[1]) and
+    // the rounding is redone with the eager fallback if it was set.
+    bool lazy_qr = false;
+    int* qr_sticky = nullptr;
     double* host = nullptr;  // pinned scalars
     int* host_int = nullptr;
     int zeroed_qrcnt = 0, zeroed_sumcnt = 0;
@@ -80,6 +86,13 @@ struct Workspace {
         }
         return p;
     }
+    void begin_lazy_qr(hipStream_t s) {
+        qr_sticky = qrsticky.as<int>(16);
+        launch_fill_int(qr_sticky, 0, 16, s);
+        host_int[1] = 0;
+        lazy_qr = true;
+    }
+    void end_lazy_qr() { lazy_qr = false; }
     int* sum_counter(hipStream_t s) {
         const size_t before = sumcnt.cap;
         int* p = sumcnt.as<int>(16);
@@ -179,8 +192,21 @@ void gemm_args(Workspace& ws, hipStream_t s, const GemmArgs& g) {
 
 double read_scalar(Workspace& ws, hipStream_t s, const double* dev) {
     TTR_HIP(hipMemcpyAsync(ws.host, dev, sizeof(double), hipMemcpyDeviceToHost, s));
+    if (ws.lazy_qr)
+        TTR_HIP(hipMemcpyAsync(ws.host_int + 1, ws.qr_sticky, sizeof(int), hipMemcpyDeviceToHost, s));
     TTR_HIP(hipStreamSynchronize(s));
     return ws.host[0];
+}
+
+// Lazy-QR mode: has a CholeskyQR broken down since begin_lazy_qr (as of the
+// last scalar readback or final_sync)?
+bool qr_broke(const Workspace& ws) { return ws.lazy_qr && ws.host_int[1] != 0; }
+
+// End-of-rounding synchronisation that also fetches the breakdown flag.
+void final_sync(Workspace& ws, hipStream_t s) {
+    if (ws.lazy_qr)
+        TTR_HIP(hipMemcpyAsync(ws.host_int + 1, ws.qr_sticky, sizeof(int), hipMemcpyDeviceToHost, s));
+    TTR_HIP(hipStreamSynchronize(s));
 }
 
 int read_int(Workspace& ws, hipStream_t s, const int* dev) {
@@ -190,16 +216,20 @@ int read_int(Workspace& ws, hipStream_t s, const int* dev) {
 }
 
 // Thin QR: CholeskyQR2 when the panel is certified well conditioned, else
-// (decided on the device) Householder TSQR on the untouched panel.
+// (decided on the device) Householder TSQR on the untouched panel.  In
+// lazy-QR mode the Householder kernels are not launched: a breakdown only
+// raises the workspace's sticky flag (the caller redoes its rounding).
 void qr(Workspace& ws, hipStream_t s, double* a, int m, int b, int lda, double* r_out = nullptr) {
     const QrPlan p = plan_qr(m, b, lda);
     TimedScope ts(KT_QR, s);
     int* cnt = ws.qr_counters(p.nodes + 8, s);
     int* flags = cnt + p.nodes + 4;  // route flags, set by the fast path
     double* cw = ws.cqws.as<double>(cq_workspace_doubles(m, b));
-    launch_cq(a, m, b, lda, r_out, cw, flags, s);
-    double* w = ws.qrws.as<double>(qr_workspace_doubles(p));
-    launch_qr(p, a, r_out, w, cnt, s, flags);
+    launch_cq(a, m, b, lda, r_out, cw, flags, s, ws.lazy_qr ? ws.qr_sticky : nullptr);
+    if (!ws.lazy_qr) {
+        double* w = ws.qrws.as<double>(qr_workspace_doubles(p));
+        launch_qr(p, a, r_out, w, cnt, s, flags);
+    }
     static const bool trace = std::getenv("TTR_TRACE_QR") != nullptr;
     if (trace) {
         const int f = read_int(ws, s, flags);
@@ -664,15 +694,28 @@ size_t workspace_bytes(const Shape& s, int64_t ell_max, int prec) {
 // ---------------------------------------------------------------------------
 // Fixed rank (Sec. 3.2)
 // ---------------------------------------------------------------------------
-void round_fixed(const Summands& x, const int64_t* target, int64_t ell, uint64_t seed,
-                 const Options& o, OutCores& y, RoundInfo& info) {
+// TTR_FORCE_QR_RETRY (read per call): repeat every rounding as if a QR had
+// broken down, so tests can run the repeat path on well-posed inputs.
+static bool force_qr_retry() { return std::getenv("TTR_FORCE_QR_RETRY") != nullptr; }
+
+// Lazy-QR mode for the duration of one rounding attempt (always left off).
+struct LazyQr {
+    Workspace& ws;
+    LazyQr(Workspace& w, hipStream_t s, bool on) : ws(w) {
+        if (on) ws.begin_lazy_qr(s);
+    }
+    ~LazyQr() { ws.end_lazy_qr(); }
+    LazyQr(const LazyQr&) = delete;
+    LazyQr& operator=(const LazyQr&) = delete;
+};
+
+// One attempt of the fixed-rank rounding; false if a CholeskyQR broke down
+// in lazy-QR mode (the outputs are then incomplete).
+static bool round_fixed_once(Workspace& ws, const Summands& x, const int64_t* target, int64_t ell,
+                             uint64_t seed, const Options& o, OutCores& y, RoundInfo& info) {
     const Shape& s = x.fs;
     const int d = s.d;
-    if (ell < 1) throw Error(-1, "ell must be >= 1");
-    if (ell > 64) throw Error(-6, "fixed-rank sketch size ell > 64 is not supported");
     hipStream_t st = o.stream;
-    WsLease lease;
-    Workspace& ws = *lease.ws;
 
     std::vector<int64_t> l(d + 1, 1);
     for (int k = 1; k < d; ++k) l[k] = std::min<int64_t>({ell, l[k - 1] * s.n[k - 1], s.r[k]});
@@ -714,9 +757,28 @@ void round_fixed(const Summands& x, const int64_t* target, int64_t ell, uint64_t
         recompress(ws, st, s, y.cores, y.ranks, -1.0, tg.data());
         y.orth = 2;
     }
-    TTR_HIP(hipStreamSynchronize(st));
+    final_sync(ws, st);
     info = RoundInfo{};
     info.passes = sk.passes;
+    return !qr_broke(ws);
+}
+
+// The first attempt defers the Householder fallback of every QR (one flag
+// checked when the rounding ends); a breakdown, which none of the measured
+// workloads hits, repeats the rounding with the fallback launched per QR.
+void round_fixed(const Summands& x, const int64_t* target, int64_t ell, uint64_t seed,
+                 const Options& o, OutCores& y, RoundInfo& info) {
+    if (ell < 1) throw Error(-1, "ell must be >= 1");
+    if (ell > 64) throw Error(-6, "fixed-rank sketch size ell > 64 is not supported");
+    WsLease lease;
+    const bool force = force_qr_retry();
+    for (int attempt = 0; attempt < 2; ++attempt) {
+        LazyQr lq(*lease.ws, o.stream, attempt == 0);
+        if (round_fixed_once(*lease.ws, x, target, ell, seed, o, y, info) && !(force && attempt == 0)) {
+            info.qr_retries = attempt;
+            return;
+        }
+    }
 }
 
 void round_fixed(const Shape& s, const double* const* cores, const int64_t* target, int64_t ell,
@@ -727,14 +789,13 @@ void round_fixed(const Shape& s, const double* const* cores, const int64_t* targ
 // ---------------------------------------------------------------------------
 // Adaptive rank (Sec. 3.3)
 // ---------------------------------------------------------------------------
-void round_adaptive(const Summands& x, double tol, int64_t ell_block, uint64_t seed,
-                    const Options& o, OutCores& y, RoundInfo& info) {
+// One attempt of the adaptive rounding; false if a CholeskyQR broke down in
+// lazy-QR mode (seen at a scalar readback or at the end).
+static bool round_adaptive_once(Workspace& ws, const Summands& x, double tol, int64_t ell_block,
+                                uint64_t seed, const Options& o, OutCores& y, RoundInfo& info) {
     const Shape& s = x.fs;
     const int d = s.d;
-    if (!(tol > 0.0)) throw Error(-1, "tol must be > 0");
     hipStream_t st = o.stream;
-    WsLease lease;
-    Workspace& ws = *lease.ws;
     const double f_init = (o.f_init > 0.0) ? o.f_init : 0.1;
 
     const std::vector<int64_t> cap = rank_caps(s);
@@ -809,6 +870,7 @@ void round_adaptive(const Summands& x, double tol, int64_t ell_block, uint64_t s
             gemm(ws, st, ncq, bb, rows, Q, rows, 1, S, 1, rows, T, bb, 1);
             gemm(ws, st, rows, bb, ncq, Q, 1, rows, T, bb, 1, S, 1, rows, -1.0, 1.0);
             const double est = std::sqrt(sumsq(ws, st, S, 1, rows, rows, bb) / (double)bb);
+            if (qr_broke(ws)) return false;
             info.iterations++;
             if (tau > 0) info.min_margin = std::min(info.min_margin, std::fabs(est - tau) / tau);
             if (!(est > tau)) break;
@@ -833,9 +895,26 @@ void round_adaptive(const Summands& x, double tol, int64_t ell_block, uint64_t s
         recompress(ws, st, s, y.cores, y.ranks, tau, nullptr);
         y.orth = 2;
     }
-    TTR_HIP(hipStreamSynchronize(st));
+    final_sync(ws, st);
     info.passes = sk.passes;
     if (info.iterations == 0) info.min_margin = INFINITY;
+    return !qr_broke(ws);
+}
+
+// Deferred Householder fallback as in round_fixed; the breakdown flag is
+// also read with every estimator readback, so a failed attempt stops early.
+void round_adaptive(const Summands& x, double tol, int64_t ell_block, uint64_t seed,
+                    const Options& o, OutCores& y, RoundInfo& info) {
+    if (!(tol > 0.0)) throw Error(-1, "tol must be > 0");
+    WsLease lease;
+    const bool force = force_qr_retry();
+    for (int attempt = 0; attempt < 2; ++attempt) {
+        LazyQr lq(*lease.ws, o.stream, attempt == 0);
+        if (round_adaptive_once(*lease.ws, x, tol, ell_block, seed, o, y, info) && !(force && attempt == 0)) {
+            info.qr_retries = attempt;
+            return;
+        }
+    }
 }
 
 void round_adaptive(const Shape& s, const double* const* cores, double tol, int64_t ell_block,

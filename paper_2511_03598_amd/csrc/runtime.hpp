@@ -25,6 +25,7 @@ struct Options {
 struct RoundInfo {
     double tau = 0, nrmx = 0, min_margin = 0;
     int passes = 0, iterations = 0;
+    int qr_retries = 0;  // 1: repeated with the eager Householder fallback
 };
 
 // Output cores: caller-owned device buffers with capacities (elements).

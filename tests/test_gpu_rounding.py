@@ -188,3 +188,39 @@ def test_adaptive_sketch_precision_does_not_floor(lib, tol):
             ref = info
         assert info["ranks"] == ref["ranks"]
         assert info["iterations"] == ref["iterations"]
+
+
+def test_lazy_qr_fallback_repeat_path(lib, monkeypatch):
+    """Roundings defer the Householder fallback of their QRs and repeat the
+    whole rounding with the fallback launched per QR if any CholeskyQR broke
+    down.  TTR_FORCE_QR_RETRY runs that repeat on a well-posed input: it is
+    reported in qr_retries and gives bitwise the same result (the fallback
+    kernels do nothing when no QR breaks down), for the fixed-rank and the
+    adaptive rounding (whose own first attempt may already have broken
+    down)."""
+    x = ttgen.small_random(7, 6, 16, 24)
+    xd = to_dev(x)
+    yf, inf = lib.round_fixed(xd, 20, 42, target_ranks=[1] + [15] * 5 + [1])
+    ya, ina = lib.round_adaptive(xd, 1e-8, 4, 42)
+    assert inf["qr_retries"] == 0          # Gaussian-like sketches: no breakdown
+    assert ina["qr_retries"] in (0, 1)     # the last blocks may be rank-deficient
+    monkeypatch.setenv("TTR_FORCE_QR_RETRY", "1")
+    yf2, inf2 = lib.round_fixed(xd, 20, 42, target_ranks=[1] + [15] * 5 + [1])
+    ya2, ina2 = lib.round_adaptive(xd, 1e-8, 4, 42)
+    assert inf2["qr_retries"] == 1 and ina2["qr_retries"] == 1
+    assert inf2["ranks"] == inf["ranks"] and ina2["ranks"] == ina["ranks"]
+    for a, b in zip(to_host(yf), to_host(yf2)):
+        assert np.array_equal(a, b)
+    for a, b in zip(to_host(ya), to_host(ya2)):
+        assert np.array_equal(a, b)
+
+
+def test_rank_deficient_sketch_rounding_exact(lib):
+    """ell = 12 above C1's exact ranks 10: the sketch is rank-deficient, which
+    the shifted CholeskyQR3 route (or, on a breakdown, the repeat with the
+    Householder fallback) absorbs; the rounding still recovers X exactly."""
+    x = ttgen.c1()
+    y, info = lib.round_fixed(to_dev(x), 12, 42, target_ranks=[1] + [10] * 5 + [1])
+    say("rank-deficient sketch: qr_retries", info["qr_retries"])
+    assert info["qr_retries"] in (0, 1)
+    assert tt.rel_err(x, to_host(y)) < 1e-12
