@@ -155,9 +155,11 @@ def main():
         y, info = step()
     torch.cuda.synchronize()
     # Timed region: K whole roundings, with the library's HIP-event timers on
-    # (event pairs on this stream around each partial-contraction launch and
-    # around each GEMM, QR and SVD).
-    ttr.kernel_timing(True)
+    # around each partial-contraction launch only (the roofline's launch
+    # duration); the breakdown over all kernel kinds comes from a separate
+    # untimed pass, since event pairs around every GEMM, QR and SVD add about
+    # a tenth to the rounding time.
+    ttr.kernel_timing(True, kinds=["partial_contraction"])
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -172,6 +174,13 @@ def main():
     ms_per_step = gpu_ms / args.steps
     value = args.steps / (gpu_ms / 1e3)
     kt = {k: ttr.kernel_timing_read(k) for k in ttr.KERNEL_KINDS}
+    # per-kind breakdown (untimed pass with every kind's timers on)
+    ttr.kernel_timing(True)
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    ttr.kernel_timing(False)
+    kbreak = {k: ttr.kernel_timing_read(k)[1] / args.steps for k in ttr.KERNEL_KINDS}
 
     # Roofline of the partial-contraction kernel: algorithmic bytes of one
     # pass / launches per pass, over the average recorded launch duration.
@@ -204,7 +213,7 @@ def main():
                      "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic,
                      "kernel": "partial contraction (pc_kernel<float>)",
                      "bytes_per_launch": pc_bytes / npc, "avg_launch_us": avg_launch_s * 1e6},
-        "kernel_ms_per_step": {k: v[1] / args.steps for k, v in kt.items()},
+        "kernel_ms_per_step": kbreak,
         "wall_s": wall,
     }
     if not args.no_parity:
@@ -296,12 +305,15 @@ def run_sum(args):
         for _ in range(max(1, args.warmup)):
             run(kind)
         torch.cuda.synchronize()
-        ttr.kernel_timing(True)
         t0 = time.perf_counter()
         for _ in range(args.steps):
             out = run(kind)
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t0) / args.steps
+        ttr.kernel_timing(True)  # breakdown in a separate pass
+        for _ in range(args.steps):
+            run(kind)
+        torch.cuda.synchronize()
         ttr.kernel_timing(False)
         kms = {k: ttr.kernel_timing_read(k)[1] / args.steps for k in ttr.KERNEL_KINDS}
         res[kind] = out
@@ -363,7 +375,7 @@ def run_precision(args):
             for _ in range(max(1, args.warmup)):
                 ttr.round_adaptive(big, tol, 16, 42, prec=prec)
             torch.cuda.synchronize()
-            ttr.kernel_timing(True)
+            ttr.kernel_timing(True, kinds=["partial_contraction"])
             t0 = time.perf_counter()
             for _ in range(args.steps):
                 y, info = ttr.round_adaptive(big, tol, 16, 42, prec=prec)

@@ -298,9 +298,13 @@ typedef enum {
     TT_KERNEL_KINDS = 4
 } tt_kernel_kind;
 
-/* enable != 0: clear the counters and start recording; 0: stop recording
- * (recorded pairs stay readable). */
-tt_status tt_kernel_timing(int32_t enable);
+/* kinds != 0: clear the counters and start recording the kinds whose bit
+ * (1 << tt_kernel_kind) is set, e.g. TT_KERNEL_TIMING_ALL; 0: stop
+ * recording (recorded pairs stay readable).  Every recorded pair adds a
+ * little time on the stream, so a measurement that only needs one kind
+ * should record only that kind.  TT_EINVAL for bits beyond the kinds. */
+#define TT_KERNEL_TIMING_ALL ((1 << TT_KERNEL_KINDS) - 1)
+tt_status tt_kernel_timing(int32_t kinds);
 
 /* Launches recorded for `kind` and their summed duration in milliseconds;
  * waits for the recorded events to complete.  TT_EINVAL on a bad kind or

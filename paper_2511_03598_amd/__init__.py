@@ -346,10 +346,17 @@ def qr(a, stream=None):
 KERNEL_KINDS = {"partial_contraction": 0, "gemm": 1, "qr": 2, "svd": 3}
 
 
-def kernel_timing(enable):
+def kernel_timing(enable, kinds=None):
     """Start (clearing the counters) or stop recording HIP events around the
-    library's launches of each kernel kind."""
-    _check(lib().tt_kernel_timing(1 if enable else 0))
+    library's launches.  kinds: names from KERNEL_KINDS to record (default
+    all); each recorded pair costs a little stream time, so a measurement
+    that needs one kind should name only that kind."""
+    mask = 0
+    if enable:
+        names = KERNEL_KINDS if kinds is None else kinds
+        for k in names:
+            mask |= 1 << KERNEL_KINDS[k]
+    _check(lib().tt_kernel_timing(mask))
 
 
 def kernel_timing_read(kind):

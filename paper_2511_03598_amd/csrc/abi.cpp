@@ -321,8 +321,11 @@ tt_status tt_svd_small(const double* a, int64_t p, int64_t q, double* g, double*
     });
 }
 
-tt_status tt_kernel_timing(int32_t enable) {
-    return guarded([&] { ttr::timing_enable(enable != 0); });
+tt_status tt_kernel_timing(int32_t kinds) {
+    return guarded([&] {
+        if (kinds < 0 || kinds > TT_KERNEL_TIMING_ALL) throw ttr::Error(TT_EINVAL, "unknown kernel kinds");
+        ttr::timing_enable((unsigned)kinds);
+    });
 }
 
 tt_status tt_kernel_timing_read(int32_t kind, int64_t* launches, double* total_ms) {

@@ -990,7 +990,7 @@ int64_t svd_small(const double* a, int64_t p, int64_t q, double* g, double* v, d
 namespace {
 struct TimingState {
     std::mutex mu;
-    bool on = false;
+    unsigned kinds = 0;  // bit k: record kind k
     struct Rec {
         hipEvent_t e0, e1;
         int launches;
@@ -1033,17 +1033,17 @@ hipEvent_t take_event(TimingState& t) {
 }
 }  // namespace
 
-void timing_enable(bool on) {
+void timing_enable(unsigned kinds) {
     TimingState& t = timing();
     std::lock_guard<std::mutex> lk(t.mu);
-    if (on) {
+    if (kinds) {
         for (int k = 0; k < KT_KINDS; ++k) {
             drain(t, k);
             t.launches[k] = 0;
             t.ms[k] = 0.0;
         }
     }
-    t.on = on;
+    t.kinds = kinds;
 }
 
 void timing_read(int kind, int64_t* launches, double* total_ms) {
@@ -1059,7 +1059,7 @@ TimedScope::TimedScope(int kind, hipStream_t s, int launches)
     : kind_(kind), s_(s), launches_(launches) {
     TimingState& t = timing();
     std::lock_guard<std::mutex> lk(t.mu);
-    if (!t.on) return;
+    if (!((t.kinds >> kind) & 1u)) return;
     e0_ = take_event(t);
     if (e0_ && hipEventRecord(e0_, s_) != hipSuccess) {
         (void)hipGetLastError();

@@ -83,7 +83,7 @@ int64_t svd_small(const double* a, int64_t p, int64_t q, double* g, double* v, d
 // Kernel timing: HIP event pairs around launches of each kind (see
 // tt_kernel_timing in the C header).
 enum { KT_PC = 0, KT_GEMM = 1, KT_QR = 2, KT_SVD = 3, KT_KINDS = 4 };
-void timing_enable(bool on);
+void timing_enable(unsigned kinds);  // bit k records kind k; 0 stops
 void timing_read(int kind, int64_t* launches, double* total_ms);
 
 // RAII scope: records a start event on construction and a stop event on

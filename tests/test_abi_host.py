@@ -91,14 +91,17 @@ def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
 
 
 def test_kernel_timing_host_only():
-    """Enabling, disabling and reading the timers makes no device call when
-    nothing was launched; a bad kind is rejected."""
+    """Enabling (a mask of kinds), disabling and reading the timers makes no
+    device call when nothing was launched; bad kinds are rejected."""
     import paper_2511_03598_amd as ttr
     L = ttr.lib()
     assert L.tt_kernel_timing(1) == 0
     n, ms = ctypes.c_int64(-1), ctypes.c_double(-1.0)
     assert L.tt_kernel_timing_read(0, ctypes.byref(n), ctypes.byref(ms)) == 0
     assert n.value == 0 and ms.value == 0.0
+    assert L.tt_kernel_timing(0) == 0
+    assert L.tt_kernel_timing(0xF) == 0  # every kind
+    assert L.tt_kernel_timing(0x10) == -1 and L.tt_kernel_timing(-1) == -1  # unknown kinds
     assert L.tt_kernel_timing(0) == 0
     assert L.tt_kernel_timing_read(7, ctypes.byref(n), ctypes.byref(ms)) == -1
     assert L.tt_kernel_timing_read(0, None, ctypes.byref(ms)) == -1
