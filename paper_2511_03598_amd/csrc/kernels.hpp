@@ -131,8 +131,11 @@ void launch_cq(double* a, int m, int b, int lda, double* r_out, double* ws, int*
 // (q x q, ld q) the matching right singular vectors, sig[q] the singular
 // values, and *t_out the kept rank: the smallest t >= 1 whose tail
 // sqrt(sum_{j>=t} sig_j^2) <= tau if tau >= 0, else min(max(target,1), q).
+// trans: A is given transposed, element (i, c) at A[i * lda + c] (a
+// row-major p x q matrix, or the column-major R whose R^T is wanted).
 void launch_svd_jacobi(const double* A, int lda, int p, int q, double* G, double* Vs,
-                       double* sig, double tau, int target, int* t_out, hipStream_t s);
+                       double* sig, double tau, int target, int* t_out, hipStream_t s,
+                       bool trans = false);
 
 int device_lds_limit();
 

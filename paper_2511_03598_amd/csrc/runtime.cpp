@@ -511,40 +511,42 @@ void next_core(Workspace& ws, hipStream_t st, const Summands& x, int k, const do
 
 // Right-to-left truncation pass (Remark 2) on caller cores in place.  tau >=
 // 0 selects the tail rule, else target ranks (host [d+1]).
+// The core being truncated lives in one of two scratch buffers (the sweep
+// ping-pong, free by now): step k factors its core there, writes the
+// truncated core k straight into cores[k-1] and the updated core k-1 into
+// the other buffer, so only the first and the last core are copied.
 void recompress(Workspace& ws, hipStream_t st, const Shape& s, double** cores, int64_t* ranks,
                 double tau, const int64_t* target) {
     const int d = s.d;
-    int64_t maxcore = 0, maxrows = 0;
-    for (int k = 1; k <= d; ++k) {
-        maxcore = std::max(maxcore, ranks[k - 1] * s.n[k - 1] * ranks[k]);
-        maxrows = std::max(maxrows, ranks[k - 1] * s.n[k - 1]);
-    }
-    double* tmp = ws.tmp.as<double>(maxcore + 64);
+    int64_t maxcore = 0;
+    for (int k = 1; k <= d; ++k) maxcore = std::max(maxcore, ranks[k - 1] * s.n[k - 1] * ranks[k]);
+    double* buf[2] = {ws.y0.as<double>(maxcore + 64), ws.y1.as<double>(maxcore + 64)};
+    int cb = 0;
+    TTR_HIP(hipMemcpyAsync(buf[0], cores[d - 1], (size_t)(ranks[d - 1] * s.n[d - 1] * ranks[d]) * sizeof(double),
+                           hipMemcpyDeviceToDevice, st));
     for (int k = d; k >= 2; --k) {
         const int b = (int)ranks[k - 1];
         const int m = (int)(s.n[k - 1] * ranks[k]);
-        double* H = cores[k - 1];  // b x m row-major
+        double* H = buf[cb];  // b x m row-major
         if (b > 64) throw Error(-6, "recompression supports ranks <= 64");
-        double* A = ws.small1.as<double>((size_t)b * b + 64);
         double* G = ws.small2.as<double>((size_t)b * b + 64);
         double* Vs = ws.small3.as<double>((size_t)b * b + 64);
         double* sig = ws.small4.as<double>(b + 64);
         int* tdev = ws.tint.as<int>(16);
+        const int tgt = target ? (int)target[k - 1] : 0;
         int q;
         if (m >= b) {
-            // H^T (m x b, column-major) is the row-major H buffer itself.
+            // H^T (m x b, column-major) is the row-major H buffer itself; the
+            // SVD reads R^T straight from the column-major R.
             double* R = ws.tbuf.as<double>((size_t)b * b + 64);
             qr(ws, st, H, m, b, m, R);
-            launch_copy2d(R, b, 1, A, 1, b, b, b, 1.0, st);  // A = R^T, ld b
             q = b;
-        } else {
-            launch_copy2d(H, m, 1, A, 1, b, b, m, 1.0, st);  // A = H (b x m), ld b
-            q = m;
-        }
-        const int tgt = target ? (int)target[k - 1] : 0;
-        {
             TimedScope ts(KT_SVD, st);
-            launch_svd_jacobi(A, b, b, q, G, Vs, sig, tau, tgt, tdev, st);
+            launch_svd_jacobi(R, b, b, q, G, Vs, sig, tau, tgt, tdev, st, true);
+        } else {
+            q = m;
+            TimedScope ts(KT_SVD, st);
+            launch_svd_jacobi(H, m, b, q, G, Vs, sig, tau, tgt, tdev, st, true);
         }
         // a target rank is known on the host; the tail rule needs the device
         const int t = (tau >= 0.0) ? read_int(ws, st, tdev) : std::min(std::max(tgt, 1), q);
@@ -552,20 +554,20 @@ void recompress(Workspace& ws, hipStream_t st, const Shape& s, double** cores, i
         if (trace)
             std::fprintf(stderr, "ttr svd p=%d q=%d kept=%d sweeps=%d\n", b, q, t,
                          read_int(ws, st, tdev + 1));
-        // New H(Y_k) = V_t^T Q^T (t x m) or V_t^T when m < b.
+        // Truncated core k: H(Y_k) = V_t^T Q^T (t x m), or V_t^T when m < b.
         if (m >= b) {
-            gemm(ws, st, t, m, b, Vs, q, 1, H, m, 1, tmp, m, 1);
+            gemm(ws, st, t, m, b, Vs, q, 1, H, m, 1, cores[k - 1], m, 1);
         } else {
-            launch_copy2d(Vs, q, 1, tmp, m, 1, t, m, 1.0, st);
+            launch_copy2d(Vs, q, 1, cores[k - 1], m, 1, t, m, 1.0, st);
         }
-        TTR_HIP(hipMemcpyAsync(H, tmp, (size_t)t * m * sizeof(double), hipMemcpyDeviceToDevice, st));
-        // V(Y_{k-1}) <- V(Y_{k-1}) G_t.
+        // Updated core k-1: V(Y_{k-1}) G_t, into the other buffer.
         const int rows = (int)(ranks[k - 2] * s.n[k - 2]);
-        gemm(ws, st, rows, t, b, cores[k - 2], b, 1, G, 1, b, tmp, t, 1);
-        TTR_HIP(hipMemcpyAsync(cores[k - 2], tmp, (size_t)rows * t * sizeof(double),
-                               hipMemcpyDeviceToDevice, st));
+        gemm(ws, st, rows, t, b, cores[k - 2], b, 1, G, 1, b, buf[1 - cb], t, 1);
+        cb = 1 - cb;
         ranks[k - 1] = t;
     }
+    TTR_HIP(hipMemcpyAsync(cores[0], buf[cb], (size_t)(ranks[0] * s.n[0] * ranks[1]) * sizeof(double),
+                           hipMemcpyDeviceToDevice, st));
 }
 
 void check_capacity(const Shape& s, const std::vector<int64_t>& l, const OutCores& y) {

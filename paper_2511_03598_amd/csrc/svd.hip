@@ -53,7 +53,7 @@ __device__ __forceinline__ void jacobi_cs(double al, double be, double ga, doubl
     s = copysign(1.0, dd) * g2 * h;
 }
 
-__global__ void __launch_bounds__(512) svd_jacobi_kernel(const double* A, int lda, int p, int q,
+__global__ void __launch_bounds__(512) svd_jacobi_kernel(const double* A, int lda, int trans, int p, int q,
                                                          double* G, double* Vs, double* sig,
                                                          double tau, int target, int* t_out) {
     // Columns of A and V live in LDS with a fixed stride of 64 rows, zero
@@ -70,7 +70,7 @@ __global__ void __launch_bounds__(512) svd_jacobi_kernel(const double* A, int ld
     double amax = 0.0;
     for (int t = tid; t < 64 * LD; t += 512) {
         const int c = t / LD, i = t - c * LD;
-        const double a = (c < q && i < p) ? A[(size_t)c * lda + i] : 0.0;
+        const double a = (c < q && i < p) ? A[trans ? (size_t)i * lda + c : (size_t)c * lda + i] : 0.0;
         As[t] = a;
         amax = fmax(amax, fabs(a));
         V[t] = (c == i && c < q) ? 1.0 : 0.0;
@@ -210,10 +210,10 @@ __global__ void __launch_bounds__(512) svd_jacobi_kernel(const double* A, int ld
 }  // namespace
 
 void launch_svd_jacobi(const double* A, int lda, int p, int q, double* G, double* Vs, double* sig,
-                       double tau, int target, int* t_out, hipStream_t s) {
+                       double tau, int target, int* t_out, hipStream_t s, bool trans) {
     if (q < 1 || q > 64 || p < q || p > 64)
         throw Error(-6, "small SVD: need 1 <= q <= p <= 64");
-    hipLaunchKernelGGL(svd_jacobi_kernel, dim3(1), dim3(512), 0, s, A, lda, p, q, G, Vs, sig,
+    hipLaunchKernelGGL(svd_jacobi_kernel, dim3(1), dim3(512), 0, s, A, lda, trans ? 1 : 0, p, q, G, Vs, sig,
                        tau, target, t_out);
     TTR_CHECK_LAUNCH();
 }
