@@ -31,7 +31,8 @@ namespace {
 constexpr int TB = 64;       // rows per LDS tile
 constexpr int LDT = 64 + 1;  // padded row stride (doubles)
 
-// flags[0]: 1 = fall back to Householder; flags[1]: 1 = shifted route.
+// flags[0]: 1 = fall back to Householder; flags[1]: 1 = shifted route;
+// flags[2]: bit p-2 set when pass p used the near-identity factor.
 struct CqDev {
     int m, b, lda, P;
     double* a;      // panel (m x b, column-major, lda): S in, Q out
@@ -110,7 +111,7 @@ __device__ __forceinline__ void store_partial(double* gp, const double4_t acc[4]
 
 __global__ void __launch_bounds__(256) cq_gram_kernel(CqDev q) {
     // route flags of this QR start at zero (read only by later kernels)
-    if (blockIdx.x == 0 && threadIdx.x < 2) q.flags[threadIdx.x] = 0;
+    if (blockIdx.x == 0 && threadIdx.x < 3) q.flags[threadIdx.x] = 0;
     __shared__ double T[TB * LDT];
     int r0, r1;
     block_rows(q, blockIdx.x, r0, r1);
@@ -354,6 +355,37 @@ __device__ int chol_factor(const double* G, double shift, double rel, int b, Fac
     return __syncthreads_or(bad);
 }
 
+// Factor of a Gram within 1e-9 of the identity (the second pass of
+// CholeskyQR2, or the third of the shifted route, on a well-conditioned
+// panel), without the pivot chain.  With G = I + E and U the strict upper
+// triangle of E plus half its diagonal, the exact factor is R = I + U -
+// U(R'^T R') with R' = R - I, and (I + U)^{-1} = I - U + U^2 - ..., so
+// R = I + U and R^{-1} = I - U are exact up to entries of 64 max|E|^2 <=
+// 6.4e-17, below the rounding of the factorization they replace.  Fills
+// F.L = R^T and F.X = R^{-T} as chol_factor does and returns true, or
+// returns false (F untouched) when some |E_ij| exceeds 1e-9 or is not
+// finite.  Block-uniform; every thread must call it.
+__device__ bool near_identity_factor(const double* G, int b, FactorLds& F) {
+    double gv[16];
+    bool fine = true;
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+        const int t = threadIdx.x + 256 * e, i = t >> 6, j = t & 63;
+        gv[e] = (i < b && j < b) ? G[t] : (i == j ? 1.0 : 0.0);
+        fine = fine && fabs(gv[e] - (i == j ? 1.0 : 0.0)) <= 1e-9;
+    }
+    if (!__syncthreads_and(fine)) return false;
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+        const int t = threadIdx.x + 256 * e, i = t >> 6, j = t & 63;
+        const double u = (i > j) ? gv[e] : (i == j ? 0.5 * (gv[e] - 1.0) : 0.0);
+        F.L[i * LDT + j] = (i > j) ? u : (i == j ? 1.0 + u : 0.0);
+        F.X[i * LDT + j] = (i > j) ? -u : (i == j ? 1.0 - u : 0.0);
+    }
+    __syncthreads();
+    return true;
+}
+
 // Sum of the P partial Grams: 64 workgroups of 64 entries; wave g sums the
 // partials p in [g P/4, (g+1) P/4) in order (all loads issued together, 16
 // at a time), and the four group sums are added in the order g = 0..3.
@@ -381,7 +413,8 @@ __global__ void __launch_bounds__(256) cq_reduce_kernel(CqDev q, int pass) {
 
 // Pass p (1..3): factor the pass's Gram (pass 1 with the certificate and,
 // if it fails, the shifted retry; pass 2 with the 0.5 certificate on the
-// plain route; pass 3 only on the shifted route), then out = src * R^{-1}
+// plain route; pass 3 only on the shifted route; passes 2 and 3 by the
+// near-identity factor when their Gram allows), then out = src * R^{-1}
 // per row block (MFMA) with the partial Grams of out when another pass
 // follows.  Pass 1 reads S and writes Q1; pass 2 reads Q1 and writes Q2 or,
 // on the plain route, the final Q into the panel; pass 3 reads Q2 and writes
@@ -404,9 +437,11 @@ __global__ void __launch_bounds__(256) cq_apply_kernel(CqDev q, int pass) {
 
     double shift = 0.0;
     double rel = (pass == 1) ? 1e-10 : ((pass == 2 && !shifted_in) ? 0.5 : 0.0);
-    int bad;
+    int bad = 0;
+    // a later pass whose Gram is within 1e-9 of I needs no pivot chain
+    const bool near_id = pass >= 2 && near_identity_factor(q.g, b, F);
 #pragma unroll 1
-    for (int attempt = 0;; ++attempt) {
+    for (int attempt = 0; !near_id; ++attempt) {
         bad = chol_factor(q.g, shift, rel, b, F);
         if (pass != 1 || !bad || attempt == 1) break;
         double tr = 0.0;
@@ -422,6 +457,7 @@ __global__ void __launch_bounds__(256) cq_apply_kernel(CqDev q, int pass) {
             if (q.sticky) *q.sticky = 1;
         }
         if (tid == 0 && pass == 1) q.flags[1] = shifted ? 1 : 0;
+        if (tid == 0 && near_id) q.flags[2] |= 1 << (pass - 2);
         double* rf = q.rfac + (size_t)(pass - 1) * 4096;  // R(j, i) = L(i, j)
 #pragma unroll
         for (int e = 0; e < 16; ++e) {

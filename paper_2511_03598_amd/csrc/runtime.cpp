@@ -234,8 +234,9 @@ void qr(Workspace& ws, hipStream_t s, double* a, int m, int b, int lda, double* 
     if (trace) {
         const int f = read_int(ws, s, flags);
         const int sh = read_int(ws, s, flags + 1);
-        std::fprintf(stderr, "ttr qr m=%d b=%d route=%s\n", m, b,
-                     f ? "householder" : (sh ? "shifted-cholqr3" : "cholqr2"));
+        const int ni = read_int(ws, s, flags + 2);
+        std::fprintf(stderr, "ttr qr m=%d b=%d route=%s near_identity_passes=%d\n", m, b,
+                     f ? "householder" : (sh ? "shifted-cholqr3" : "cholqr2"), ni);
     }
 }
 
