@@ -112,6 +112,25 @@ def test_qr_matches_householder(lib, m, b):
     assert np.max(np.abs(q - ref)) < 1e-11
 
 
+@pytest.mark.parametrize("cond", [1e2, 1e3, 1e5, 1e7])
+def test_qr_second_pass_both_factor_paths(lib, cond):
+    """After the first CholeskyQR pass the Gram is I + E with |E| about
+    eps cond^2: below the near-identity bound 1e-9 for cond 1e2 and 1e3
+    (closed-form factor), above it for 1e5 and 1e7 (pivoted Cholesky; 1e7
+    also takes the shifted route).  Every case must give the positive-
+    diagonal Householder Q and an orthonormal panel."""
+    import torch
+    rng = np.random.default_rng(int(np.log10(cond)))
+    m, b = 3840, 60
+    u, _ = np.linalg.qr(rng.standard_normal((m, b)))
+    v, _ = np.linalg.qr(rng.standard_normal((b, b)))
+    a = (u * np.geomspace(1.0, 1.0 / cond, b)[None, :]) @ v.T
+    q = lib.qr(torch.tensor(a, device="cuda")).cpu().numpy()
+    ref = krp.qr_pos(a)
+    assert np.max(np.abs(q.T @ q - np.eye(b))) < 1e-13
+    assert np.max(np.abs(q - ref)) < 1e-15 * cond * 100
+
+
 def test_qr_rank_deficient_still_orthonormal(lib):
     import torch
     rng = np.random.default_rng(3)
