@@ -234,8 +234,17 @@ __global__ void __launch_bounds__(256) gemm_reduce_kernel(GemmArgs g, int splits
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t mn = (int64_t)g.M * g.N;
     if (t >= mn) return;
+    // slice order; eight loads issued together per step
     double s = 0.0;
-    for (int z = 0; z < splits; ++z) s += partials[(size_t)z * mn + t];
+    int z = 0;
+    for (; z + 8 <= splits; z += 8) {
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = partials[(size_t)(z + u) * mn + t];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) s += v[u];
+    }
+    for (; z < splits; ++z) s += partials[(size_t)z * mn + t];
     const int row = (int)(t / g.N), col = (int)(t - (int64_t)row * g.N);
     double* c = g.C + c_offset(g, row, col);
     double val = g.alpha * s;
@@ -283,9 +292,12 @@ __device__ __forceinline__ float stored_f64(const float* p, size_t i) { return p
 __device__ __forceinline__ float stored_f64(const unsigned short* p, size_t i) { return stored_f32(p, i); }
 
 // DKW: k-steps of 4 per wave the kernel loads (4, 8 or 16: K <= 16 DKW),
-// so short products do not issue loads they do not use.
+// so short products do not issue loads they do not use.  Split-K: slice
+// z = blockIdx.z takes k in [z kchunk, (z+1) kchunk) and writes its raw
+// tile to partials[z] (M x N row-major) for gemm_reduce_kernel; without
+// partials the one slice covers K and the tile goes to C.
 template <int BT, bool EXP, bool MS, int DKW>
-__global__ void __launch_bounds__(256) gemm_direct_kernel(GemmArgs g) {
+__global__ void __launch_bounds__(256) gemm_direct_kernel(GemmArgs g, int kchunk, double* partials) {
     typedef typename BStore<BT>::T ST;
     typedef typename std::conditional<BT == 0, double, float>::type AT;  // B's arithmetic type
     __shared__ double red[4][32][33];
@@ -312,14 +324,15 @@ __global__ void __launch_bounds__(256) gemm_direct_kernel(GemmArgs g) {
         for (int j = 0; j < 2; ++j) acc[i][j] = double4_t{0, 0, 0, 0};
     // K in chunks of 16 DKW; within a chunk wave w takes its quarter of the
     // k-steps
-    for (int kb = 0; kb < g.K; kb += 16 * DKW) {
-        const int nks = (min(g.K - kb, 16 * DKW) + 3) / 4;
+    const int kbeg = blockIdx.z * kchunk, kend = min(g.K, kbeg + kchunk);
+    for (int kb = kbeg; kb < kend; kb += 16 * DKW) {
+        const int nks = (min(kend - kb, 16 * DKW) + 3) / 4;
         const int ks0 = (w * nks) / 4, ks1 = ((w + 1) * nks) / 4;
         double av[DKW][2];
         AT bs[DKW][2];
 #pragma unroll
         for (int t = 0; t < DKW; ++t) {
-            const int kc = min(kb + 4 * (ks0 + t) + lg, g.K - 1);
+            const int kc = min(kb + 4 * (ks0 + t) + lg, kend - 1);
 #pragma unroll
             for (int i = 0; i < 2; ++i) {
                 av[t][i] = g.A[(size_t)rows[i] * g.sam + (size_t)kc * g.sak];
@@ -331,7 +344,7 @@ __global__ void __launch_bounds__(256) gemm_direct_kernel(GemmArgs g) {
                 const ST* Bs = Bp + (size_t)sl * g.bstride;
 #pragma unroll
                 for (int t = 0; t < DKW; ++t) {
-                    const int kc = min(kb + 4 * (ks0 + t) + lg, g.K - 1);
+                    const int kc = min(kb + 4 * (ks0 + t) + lg, kend - 1);
 #pragma unroll
                     for (int i = 0; i < 2; ++i)
                         bs[t][i] += stored_f64(Bs, (size_t)kc * g.sbk + (size_t)cols[i] * g.sbn);
@@ -343,7 +356,7 @@ __global__ void __launch_bounds__(256) gemm_direct_kernel(GemmArgs g) {
             const int ks = ks0 + t;
             if (ks < ks1) {  // uniform per wave
                 // k beyond K: the clamped operands are finite copies; zero A's
-                const bool kok = kb + 4 * ks + lg < g.K;
+                const bool kok = kb + 4 * ks + lg < kend;
                 const double a0 = kok ? av[t][0] : 0.0, a1 = kok ? av[t][1] : 0.0;
                 double b0 = (double)bs[t][0], b1 = (double)bs[t][1];
                 if (EXP) {
@@ -370,6 +383,10 @@ __global__ void __launch_bounds__(256) gemm_direct_kernel(GemmArgs g) {
         const int row = m0 + r, col = n0 + c;
         if (row < g.M && col < g.N) {
             const double sum = ((red[0][r][c] + red[1][r][c]) + red[2][r][c]) + red[3][r][c];
+            if (partials) {
+                partials[((size_t)blockIdx.z * g.M + row) * g.N + col] = sum;
+                continue;
+            }
             double* cp = g.C + c_offset(g, row, col);
             double val = g.alpha * sum;
             if (g.beta != 0.0) val += g.beta * (*cp);
@@ -379,39 +396,72 @@ __global__ void __launch_bounds__(256) gemm_direct_kernel(GemmArgs g) {
 }
 
 template <int BT, bool EXP, int DKW>
-void launch_direct_k(const GemmArgs& g, dim3 grid, hipStream_t s) {
+void launch_direct_k(const GemmArgs& g, dim3 grid, int kchunk, double* partials, hipStream_t s) {
     if (g.bslices > 1)
-        hipLaunchKernelGGL((gemm_direct_kernel<BT, EXP, true, DKW>), grid, dim3(256), 0, s, g);
+        hipLaunchKernelGGL((gemm_direct_kernel<BT, EXP, true, DKW>), grid, dim3(256), 0, s, g, kchunk,
+                           partials);
     else
-        hipLaunchKernelGGL((gemm_direct_kernel<BT, EXP, false, DKW>), grid, dim3(256), 0, s, g);
+        hipLaunchKernelGGL((gemm_direct_kernel<BT, EXP, false, DKW>), grid, dim3(256), 0, s, g, kchunk,
+                           partials);
 }
 template <int BT, bool EXP>
-void launch_direct(const GemmArgs& g, dim3 grid, hipStream_t s) {
-    const int per_wave = ceil_div(ceil_div(std::min(g.K, 16 * DKW_MAX), 4), 4);  // busiest wave's k-steps
+void launch_direct(const GemmArgs& g, dim3 grid, int kchunk, double* partials, hipStream_t s) {
+    const int per_wave = ceil_div(ceil_div(std::min(kchunk, 16 * DKW_MAX), 4), 4);  // busiest wave's k-steps
     if (per_wave <= 4)
-        launch_direct_k<BT, EXP, 4>(g, grid, s);
+        launch_direct_k<BT, EXP, 4>(g, grid, kchunk, partials, s);
     else if (per_wave <= 8)
-        launch_direct_k<BT, EXP, 8>(g, grid, s);
+        launch_direct_k<BT, EXP, 8>(g, grid, kchunk, partials, s);
     else
-        launch_direct_k<BT, EXP, 16>(g, grid, s);
+        launch_direct_k<BT, EXP, 16>(g, grid, kchunk, partials, s);
 }
 
 }  // namespace
 
+namespace {
+bool plain_direct(int M, int N, int K) {
+    const int64_t dtiles = (int64_t)ceil_div(M, 32) * ceil_div(N, 32);
+    return K >= 1 && (K <= 16 * DKW_MAX || (K <= 64 * DKW_MAX && dtiles >= 64));
+}
+bool split_direct(int M, int N, int K) { return !plain_direct(M, N, K) && (int64_t)M * N <= 65536; }
+}  // namespace
+
+int gemm_splits(int M, int N, int K) {
+    if (M <= 0 || N <= 0 || K <= 0 || plain_direct(M, N, K)) return 1;
+    // small outputs (e.g. Q^T V(Y_k)): direct tiles, one 256-deep chunk per
+    // slice, with at most 2^18 partial doubles
+    if (split_direct(M, N, K))
+        return std::max(1, std::min({64, ceil_div(K, 16 * DKW_MAX), (int)(262144 / ((int64_t)M * N))}));
+    // tiled kernel: enough workgroups to cover the chip, K slices of >= 128
+    const int tiles = ceil_div(M, 64) * ceil_div(N, 64);
+    if (tiles < 128 && K >= 512) return std::min(64, std::min(ceil_div(K, 128), std::max(1, 256 / tiles)));
+    return 1;
+}
+
 void launch_gemm(const GemmArgs& g, int splits, double* partials, hipStream_t s) {
     if (g.M <= 0 || g.N <= 0) return;
-    // direct kernel: K <= 256, or K <= 1024 on a grid of at least 64 tiles
-    const int64_t dtiles = (int64_t)ceil_div(g.M, 32) * ceil_div(g.N, 32);
-    if (g.K >= 1 && (g.K <= 16 * DKW_MAX || (g.K <= 64 * DKW_MAX && dtiles >= 64))) {
-        dim3 grid(ceil_div(g.M, 32), ceil_div(g.N, 32));
+    // direct kernel: K <= 256, or K <= 1024 on a grid of at least 64 tiles,
+    // or split over K when the output is small
+    const bool split = split_direct(g.M, g.N, g.K) && splits > 1 && partials != nullptr;
+    if (plain_direct(g.M, g.N, g.K) || split) {
+        const int ns = split ? splits : 1;
+        const int kchunk = split ? ceil_div(ceil_div(g.K, ns), 16) * 16 : g.K;
+        const int nz = ceil_div(g.K, kchunk);  // <= ns
+        dim3 grid(ceil_div(g.M, 32), ceil_div(g.N, 32), nz);
+        double* part = split ? partials : nullptr;
         const bool ex = g.bexp != nullptr;
         if (g.Bf)
-            ex ? launch_direct<1, true>(g, grid, s) : launch_direct<1, false>(g, grid, s);
+            ex ? launch_direct<1, true>(g, grid, kchunk, part, s) : launch_direct<1, false>(g, grid, kchunk, part, s);
         else if (g.Bh)
-            ex ? launch_direct<2, true>(g, grid, s) : launch_direct<2, false>(g, grid, s);
+            ex ? launch_direct<2, true>(g, grid, kchunk, part, s) : launch_direct<2, false>(g, grid, kchunk, part, s);
         else
-            launch_direct<0, false>(g, grid, s);
+            launch_direct<0, false>(g, grid, kchunk, part, s);
         TTR_CHECK_LAUNCH();
+        if (split) {
+            const int64_t mn = (int64_t)g.M * g.N;
+            hipLaunchKernelGGL(gemm_reduce_kernel, dim3(ceil_div(mn, 256)), dim3(256), 0, s, g, nz,
+                               partials);
+            TTR_CHECK_LAUNCH();
+        }
         return;
     }
     if (g.K <= 0) splits = 1;

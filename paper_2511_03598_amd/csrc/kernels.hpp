@@ -88,6 +88,9 @@ struct GemmArgs {
 };
 // `partials` must hold splits*M*N doubles when splits > 1.
 void launch_gemm(const GemmArgs& g, int splits, double* partials, hipStream_t s);
+// K slices launch_gemm uses for an M x N x K product; the caller provides
+// splits * M * N doubles of partials when this exceeds 1.
+int gemm_splits(int M, int N, int K);
 
 // ---- small utilities (util.hip) --------------------------------------------
 // dst(i, j) = src(i, j) for a rows x cols matrix with arbitrary strides.

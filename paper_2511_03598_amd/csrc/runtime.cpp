@@ -162,13 +162,7 @@ void gemm(Workspace& ws, hipStream_t s, int M, int N, int K, const double* A, in
     g.scn = scn;
     g.alpha = alpha;
     g.beta = beta;
-    const int tiles = ceil_div(M, 64) * ceil_div(N, 64);
-    int splits = 1;
-    if (tiles < 128 && K >= 512) {
-        // enough workgroups to cover the chip, K slices of >= 128
-        splits = std::min(ceil_div(K, 128), std::max(1, 256 / tiles));
-        splits = std::min(splits, 64);
-    }
+    const int splits = gemm_splits(M, N, K);
     double* partials = nullptr;
     if (splits > 1) partials = ws.part.as<double>((size_t)splits * M * N);
     TimedScope ts(KT_GEMM, s);
@@ -178,12 +172,7 @@ void gemm(Workspace& ws, hipStream_t s, int M, int N, int K, const double* A, in
 // The same launch policy for a fully specified GemmArgs.
 void gemm_args(Workspace& ws, hipStream_t s, const GemmArgs& g) {
     if (g.M <= 0 || g.N <= 0) return;
-    const int tiles = ceil_div(g.M, 64) * ceil_div(g.N, 64);
-    int splits = 1;
-    if (tiles < 128 && g.K >= 512) {
-        splits = std::min(ceil_div(g.K, 128), std::max(1, 256 / tiles));
-        splits = std::min(splits, 64);
-    }
+    const int splits = gemm_splits(g.M, g.N, g.K);
     double* partials = nullptr;
     if (splits > 1) partials = ws.part.as<double>((size_t)splits * g.M * g.N);
     TimedScope ts(KT_GEMM, s);
