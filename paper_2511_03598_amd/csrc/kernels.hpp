@@ -136,9 +136,14 @@ void launch_cq(double* a, int m, int b, int lda, double* r_out, double* ws, int*
 // sqrt(sum_{j>=t} sig_j^2) <= tau if tau >= 0, else min(max(target,1), q).
 // trans: A is given transposed, element (i, c) at A[i * lda + c] (a
 // row-major p x q matrix, or the column-major R whose R^T is wanted).
+// split_only (with tau < 0): the caller keeps only the first t = target
+// columns of G and Vs and needs them to span the best rank-t subspaces,
+// not to be singular vectors; sweeping stops once that split is certified
+// (the kept columns of G are then orthogonal to the dropped ones, not
+// necessarily to each other, and sig holds column norms).
 void launch_svd_jacobi(const double* A, int lda, int p, int q, double* G, double* Vs,
                        double* sig, double tau, int target, int* t_out, hipStream_t s,
-                       bool trans = false);
+                       bool trans = false, bool split_only = false);
 
 int device_lds_limit();
 

@@ -532,18 +532,18 @@ void recompress(Workspace& ws, hipStream_t st, const Shape& s, double** cores, i
             qr(ws, st, H, m, b, m, R);
             q = b;
             TimedScope ts(KT_SVD, st);
-            launch_svd_jacobi(R, b, b, q, G, Vs, sig, tau, tgt, tdev, st, true);
+            launch_svd_jacobi(R, b, b, q, G, Vs, sig, tau, tgt, tdev, st, true, tau < 0.0);
         } else {
             q = m;
             TimedScope ts(KT_SVD, st);
-            launch_svd_jacobi(H, m, b, q, G, Vs, sig, tau, tgt, tdev, st, true);
+            launch_svd_jacobi(H, m, b, q, G, Vs, sig, tau, tgt, tdev, st, true, tau < 0.0);
         }
         // a target rank is known on the host; the tail rule needs the device
         const int t = (tau >= 0.0) ? read_int(ws, st, tdev) : std::min(std::max(tgt, 1), q);
         static const bool trace = std::getenv("TTR_TRACE_QR") != nullptr;
         if (trace)
-            std::fprintf(stderr, "ttr svd p=%d q=%d kept=%d sweeps=%d\n", b, q, t,
-                         read_int(ws, st, tdev + 1));
+            std::fprintf(stderr, "ttr svd p=%d q=%d kept=%d sweeps=%d chol=%d failpiv=%d\n", b, q, t,
+                         read_int(ws, st, tdev + 1), read_int(ws, st, tdev + 2), read_int(ws, st, tdev + 3));
         // Truncated core k: H(Y_k) = V_t^T Q^T (t x m), or V_t^T when m < b.
         if (m >= b) {
             gemm(ws, st, t, m, b, Vs, q, 1, H, m, 1, cores[k - 1], m, 1);

@@ -53,12 +53,211 @@ __device__ __forceinline__ void jacobi_cs(double al, double be, double ga, doubl
     s = copysign(1.0, dd) * g2 * h;
 }
 
+// Tile e of the ten 16x16 tiles on and above the diagonal of a 64x64
+// matrix: e < 4 the diagonal, then (0,1) (0,2) (0,3) (1,2) (1,3) (2,3).
+__device__ __forceinline__ int tile_i(int e) { return e < 4 ? e : (e < 7 ? 0 : (e < 9 ? 1 : 2)); }
+__device__ __forceinline__ int tile_j(int e) { return e < 4 ? e : (e < 7 ? e - 3 : (e < 9 ? e - 5 : 3)); }
+
+// Maximum over the 16 lanes of a DPP row (the butterflies of group16_sum).
+__device__ __forceinline__ double group16_max(double v) {
+    v = fmax(v, dpp_f64<0xB1>(v));
+    v = fmax(v, dpp_f64<0x4E>(v));
+    v = fmax(v, dpp_f64<0x141>(v));
+    v = fmax(v, dpp_f64<0x140>(v));
+    return v;
+}
+
+constexpr int GLD = 65;  // row stride of the Gram matrix in LDS
+// Column stride (doubles) of A and V in LDS: 64 rows plus 2 of padding, so
+// that 16 lanes reading row k of 16 consecutive columns (the MFMA operand
+// pattern of the Gram matrix) hit 16 different bank pairs.
+constexpr int CLD = 66;
+
+// Rank-t split certificate for a truncation that only needs the kept
+// subspace.  With B = A V the current columns (stride 64 in As), K the t
+// columns of largest norm and D the rest, the truncation B_K V_K^T is the
+// best rank-t approximation of A up to sin(theta) ||A|| once
+//   sin(theta) <= ||B_K^T B_D||_F / (lambda_min(B_K^T B_K) - lambda_max(B_D^T B_D)) <= 1e-13
+// (Davis-Kahan for the block split of A^T A).  Bounds used: lambda_max of
+// the D block <= its largest diagonal entry + the Frobenius norm of its
+// off-diagonal part (Weyl); lambda_min of the K block > mu, mu = that
+// bound + ||G_KD||_F / 1e-13 + a rounding margin, when its smallest diagonal
+// entry minus the Frobenius norm of its off-diagonal part exceeds mu
+// (Weyl), else when the Cholesky of G_KK - mu I keeps every pivot positive.  Columns are ranked by the
+// same squared norms (16-lane sums) and rule as the final sort, so K is
+// exactly the set the caller keeps.  The Gram matrix comes from MFMA in
+// rank order (eight waves, the ten 16x16 tiles on and above the diagonal),
+// so K is its leading t x t block.  Returns true when certified; uniform
+// over the block, every thread of the 512-thread block must call it.
+__device__ bool split_certified(const double* As, int q, int t, double* Gs, double* nd, int* ord,
+                                double (*red)[7], int* stats, bool& skip_next) {
+    constexpr int LD = CLD;
+    const int tid = threadIdx.x, w = tid >> 6, l = tid & 63, li = l & 15, lg = l >> 4;
+    const int g16 = tid >> 4, l16 = tid & 15;
+    for (int c = g16; c < q; c += 32) {
+        double s = 0.0;
+        for (int i = l16; i < 64; i += 16) s += As[c * LD + i] * As[c * LD + i];
+        s = group16_sum(s);
+        if (l16 == 0) nd[c] = s;
+    }
+    __syncthreads();
+    // ord[rank] = column, by decreasing squared norm, ties by index: thread
+    // (column tid/8, part tid%8) counts the larger norms among columns
+    // part + 8u, summed over the 8 lanes of the column; slots >= q keep their
+    // own (zero) columns
+    {
+        const int c = tid >> 3, part = tid & 7;
+        const double me = c < q ? nd[c] : 0.0;
+        int cnt = 0;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int i = part + 8 * u;
+            if (i < q) {
+                const double o = nd[i];
+                cnt += (o > me) || (o == me && i < c);
+            }
+        }
+        cnt += __builtin_amdgcn_mov_dpp(cnt, 0xB1, 0xF, 0xF, true);   // quad_perm [1,0,3,2]
+        cnt += __builtin_amdgcn_mov_dpp(cnt, 0x4E, 0xF, 0xF, true);   // quad_perm [2,3,0,1]
+        cnt += __builtin_amdgcn_mov_dpp(cnt, 0x141, 0xF, 0xF, true);  // row_half_mirror
+        if (part == 0) ord[c] = c;  // a valid column in every slot even if a NaN norm broke the ranking
+        __syncthreads();
+        if (part == 0 && c < q) ord[cnt] = c;
+    }
+    __syncthreads();
+    for (int s = 0; s < 2; ++s) {
+        const int e = w + 8 * s;
+        if (e < 10) {  // uniform per wave
+            const int I = tile_i(e), J = tile_j(e);
+            const double* ca = As + ord[I * 16 + li] * LD + lg;
+            const double* cb = As + ord[J * 16 + li] * LD + lg;
+            // two accumulators (k0 = 0, 8, ... and 4, 12, ...) halve the
+            // dependent MFMA chain
+            // dependent MFMA chain; all operands are loaded first
+            double av[16], bv[16];
+#pragma unroll
+            for (int k = 0; k < 16; ++k) {
+                av[k] = ca[4 * k];
+                bv[k] = cb[4 * k];
+            }
+            double4_t acc = {0.0, 0.0, 0.0, 0.0}, acc2 = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int k = 0; k < 16; k += 2) {
+                acc = mfma_f64_16x16x4(av[k], bv[k], acc);
+                acc2 = mfma_f64_16x16x4(av[k + 1], bv[k + 1], acc2);
+            }
+#pragma unroll
+            for (int v = 0; v < 4; ++v) acc[v] += acc2[v];
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int r = I * 16 + lg + 4 * v, c = J * 16 + li;
+                Gs[r * GLD + c] = acc[v];
+                if (I != J) Gs[c * GLD + r] = acc[v];
+            }
+        }
+    }
+    __syncthreads();
+    // ||G_KD||^2, ||offdiag G_DD||^2, ||offdiag G_KK||^2, max diag D, min
+    // and max diag K, finiteness; thread: row tid/8, columns tid%8 + 8u
+    double cross = 0.0, offd = 0.0, offk = 0.0, maxd = 0.0, mink = INFINITY, maxk = 0.0, fin = 1.0;
+    const int r = tid >> 3;
+    for (int c = tid & 7; c < q && r < q; c += 8) {
+        const double g = Gs[r * GLD + c];
+        if (!(fabs(g) < INFINITY)) fin = 0.0;
+        if (r < t && c >= t) cross += g * g;
+        if (r >= t && c >= t && r != c) offd += g * g;
+        if (r < t && c < t && r != c) offk += g * g;
+        if (r == c) {
+            if (r < t) {
+                mink = fmin(mink, g);
+                maxk = fmax(maxk, g);
+            } else {
+                maxd = fmax(maxd, g);
+            }
+        }
+    }
+    // within each 16-lane row by DPP, then across the four rows
+    cross = group16_sum(cross);
+    offd = group16_sum(offd);
+    offk = group16_sum(offk);
+    maxd = group16_max(maxd);
+    maxk = group16_max(maxk);
+    mink = -group16_max(-mink);
+    fin = -group16_max(-fin);
+#pragma unroll
+    for (int off = 16; off < 64; off <<= 1) {
+        cross += __shfl_xor(cross, off, 64);
+        offd += __shfl_xor(offd, off, 64);
+        offk += __shfl_xor(offk, off, 64);
+        maxd = fmax(maxd, __shfl_xor(maxd, off, 64));
+        maxk = fmax(maxk, __shfl_xor(maxk, off, 64));
+        mink = fmin(mink, __shfl_xor(mink, off, 64));
+        fin = fmin(fin, __shfl_xor(fin, off, 64));
+    }
+    if (l == 0) {
+        red[w][0] = cross;
+        red[w][1] = offd;
+        red[w][2] = maxd;
+        red[w][3] = mink;
+        red[w][4] = maxk;
+        red[w][5] = fin;
+        red[w][6] = offk;
+    }
+    __syncthreads();
+    cross = red[0][0], offd = red[0][1], maxd = red[0][2], mink = red[0][3], maxk = red[0][4], fin = red[0][5];
+    offk = red[0][6];
+    for (int v = 1; v < 8; ++v) {
+        cross += red[v][0];
+        offd += red[v][1];
+        maxd = fmax(maxd, red[v][2]);
+        mink = fmin(mink, red[v][3]);
+        maxk = fmax(maxk, red[v][4]);
+        fin = fmin(fin, red[v][5]);
+        offk += red[v][6];
+    }
+    const double mu = maxd + sqrt(offd) + sqrt(cross) * 1e13 + 64.0 * t * 2.3e-16 * maxk;
+    // Coupling x = ||G_KD||_F / gap above 1e-4: even at Jacobi's quadratic
+    // rate the next sweep leaves it above the 1e-13 this test needs, so the
+    // caller skips the next test.
+    skip_next = !(mink - maxd - sqrt(offd) > 1e4 * sqrt(cross));
+    if (!(fin > 0.0) || !(mink > mu) || !(mu < INFINITY)) return false;  // block-uniform
+    // lambda_min(G_KK) >= min diag - ||offdiag G_KK||_F (Weyl) often suffices
+    if (mink - sqrt(offk) > mu) return true;
+    if (tid == 0) ++stats[0];
+    // Cholesky (LDL^T) of the leading t x t block minus mu I, in place on its
+    // lower triangle: step a subtracts G_ia G_ja / G_aa from a < j <= i
+    // (thread: row a+1 + tid/8, columns a+1 + tid%8 + 8u); no entry a step
+    // writes is read in that step.
+    if (tid < t) Gs[tid * GLD + tid] -= mu;
+    __syncthreads();
+    for (int a = 0; a < t; ++a) {
+        const double piv = Gs[a * GLD + a];
+        if (!(piv > 0.0)) {  // every thread reads the same pivot
+            if (tid == 0) stats[1] += a;
+            return false;
+        }
+        const double ip = 1.0 / piv;
+        const int i = a + 1 + (tid >> 3);
+        if (i < t) {
+            const double gi = Gs[i * GLD + a] * ip;
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int j = a + 1 + (tid & 7) + 8 * u;
+                if (j <= i) Gs[i * GLD + j] -= gi * Gs[j * GLD + a];
+            }
+        }
+        __syncthreads();
+    }
+    return true;
+}
+
 __global__ void __launch_bounds__(512) svd_jacobi_kernel(const double* A, int lda, int trans, int p, int q,
                                                          double* G, double* Vs, double* sig,
-                                                         double tau, int target, int* t_out) {
-    // Columns of A and V live in LDS with a fixed stride of 64 rows, zero
-    // padded, so every lane handles exactly 4 rows without masks.
-    constexpr int LD = 64;
+                                                         double tau, int target, int* t_out,
+                                                         int split_only) {
+    // Columns of A and V live in LDS, 64 rows zero padded so every lane
+    // handles exactly 4 rows without masks, at the stride CLD.
+    constexpr int LD = CLD;
     __shared__ double As[64 * LD];
     __shared__ double V[64 * LD];
     __shared__ double sg[64];
@@ -66,6 +265,12 @@ __global__ void __launch_bounds__(512) svd_jacobi_kernel(const double* A, int ld
     __shared__ int rotated;
     __shared__ int nsweeps;
     __shared__ double wmax[8];
+    // rank-t split certificate (split_only): Gram matrix, ranks, reductions
+    __shared__ double Gs[64 * GLD];
+    __shared__ double nd[64];
+    __shared__ int ord[64];
+    __shared__ double red[8][7];
+    __shared__ int cstats[2];  // Cholesky attempts, pivots done in failed ones
     const int tid = threadIdx.x;
     double amax = 0.0;
     for (int t = tid; t < 64 * LD; t += 512) {
@@ -91,11 +296,21 @@ __global__ void __launch_bounds__(512) svd_jacobi_kernel(const double* A, int ld
     // Rotate while (x.y)^2 > tol^2 (x.x)(y.y); tol sits well above the
     // rounding error of a p-term dot product (~p u) so the sweep test can be met.
     const double tol2 = 1e-26;
-    if (tid == 0) nsweeps = 0;
+    if (tid == 0) {
+        nsweeps = 0;
+        cstats[0] = cstats[1] = 0;
+    }
     // One column pair per 16-lane group; lane l16 holds rows l16, l16+16, ...
     const int g8 = tid >> 4, l8 = tid & 15;
     __syncthreads();
-    for (int sweep = 0; sweep < 60 && q >= 2; ++sweep) {
+    // A truncation to a fixed rank tt only needs the kept subspace: with
+    // nothing to drop, any V will do (no sweep); otherwise sweeping stops
+    // once split_certified holds.  The kept columns are then orthogonal to
+    // the dropped ones but not necessarily to each other.
+    const int tt = min(max(target, 1), q);
+    const bool split = split_only && tau < 0.0;
+    bool skip_test = false;  // uniform: the last test found the split far off
+    for (int sweep = 0; sweep < 60 && q >= 2 && !(split && tt >= q); ++sweep) {
         if (tid == 0) rotated = 0;
         __syncthreads();
         // Recursive bipartite order on 64 column slots (columns >= q are
@@ -162,11 +377,17 @@ __global__ void __launch_bounds__(512) svd_jacobi_kernel(const double* A, int ld
         if (tid == 0) nsweeps = sweep + 1;
         __syncthreads();
         if (done) break;
+        if (split) {
+            if (skip_test)
+                skip_test = false;
+            else if (split_certified(As, q, tt, Gs, nd, ord, red, cstats, skip_test))
+                break;
+        }
     }
     // Column norms, sort by decreasing norm (stable by index).
     for (int c = g8; c < q; c += 32) {
         double s = 0.0;
-        for (int i = l8; i < 64; i += 16) s += As[c * 64 + i] * As[c * 64 + i];
+        for (int i = l8; i < 64; i += 16) s += As[c * LD + i] * As[c * LD + i];
         s = group16_sum(s);
         if (l8 == 0) sg[c] = ldexp(sqrt(s), sexp);
     }
@@ -180,11 +401,11 @@ __global__ void __launch_bounds__(512) svd_jacobi_kernel(const double* A, int ld
     __syncthreads();
     for (int t = tid; t < p * q; t += 512) {
         const int r = t / p, i = t - r * p;
-        G[(size_t)r * p + i] = ldexp(As[perm[r] * 64 + i], sexp);
+        G[(size_t)r * p + i] = ldexp(As[perm[r] * LD + i], sexp);
     }
     for (int t = tid; t < q * q; t += 512) {
         const int r = t / q, i = t - r * q;
-        Vs[(size_t)r * q + i] = V[perm[r] * 64 + i];
+        Vs[(size_t)r * q + i] = V[perm[r] * LD + i];
     }
     if (tid < q) sig[tid] = sg[perm[tid]];
     if (tid == 0) {
@@ -200,21 +421,24 @@ __global__ void __launch_bounds__(512) svd_jacobi_kernel(const double* A, int ld
                     break;
             }
         } else {
-            t = min(max(target, 1), q);
+            t = tt;
         }
         t_out[0] = t;
         t_out[1] = nsweeps;
+        t_out[2] = cstats[0];
+        t_out[3] = cstats[1];
     }
 }
 
 }  // namespace
 
 void launch_svd_jacobi(const double* A, int lda, int p, int q, double* G, double* Vs, double* sig,
-                       double tau, int target, int* t_out, hipStream_t s, bool trans) {
+                       double tau, int target, int* t_out, hipStream_t s, bool trans,
+                       bool split_only) {
     if (q < 1 || q > 64 || p < q || p > 64)
         throw Error(-6, "small SVD: need 1 <= q <= p <= 64");
     hipLaunchKernelGGL(svd_jacobi_kernel, dim3(1), dim3(512), 0, s, A, lda, trans ? 1 : 0, p, q, G, Vs, sig,
-                       tau, target, t_out);
+                       tau, target, t_out, split_only ? 1 : 0);
     TTR_CHECK_LAUNCH();
 }
 

@@ -105,6 +105,22 @@ def test_fixed_c2_full_size(lib, prec):
     _check_orth(yg, ig)
 
 
+@pytest.mark.parametrize("seed", [31, 32])
+def test_fixed_truncation_without_spectral_gap(lib, seed):
+    """Truncating a random TT (no gap in its bond spectra) from ell = 24 to
+    ranks 12: the Jacobi sweeps stop early only once the kept/dropped split
+    is certified, so the result must still match the oracle's exact SVD
+    truncation."""
+    say("fixed no-gap truncation", seed)
+    x = ttgen.small_random(seed, 5, 12, 30)
+    tgt = [1] + [12] * 4 + [1]
+    yg, ig = _fixed(lib, x, 24, 9, tgt)
+    yo, io = krp.round_fixed(x, 24, 9, tgt)
+    assert ig["ranks"] == io["ranks"] == tgt
+    assert rel_tensor_diff(x, yg, yo) <= TOL["f64"]
+    _check_orth(yg, ig)
+
+
 def _ranks_equal_or_tie(ig, io, rg, ro):
     if rg == ro:
         return True
