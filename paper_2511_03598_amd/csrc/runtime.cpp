@@ -211,8 +211,13 @@ int read_int(Workspace& ws, hipStream_t s, const int* dev) {
 void qr(Workspace& ws, hipStream_t s, double* a, int m, int b, int lda, double* r_out = nullptr) {
     const QrPlan p = plan_qr(m, b, lda);
     TimedScope ts(KT_QR, s);
-    int* cnt = ws.qr_counters(p.nodes + 8, s);
-    int* flags = cnt + p.nodes + 4;  // route flags, set by the fast path
+    // Route flags first (reset by every QR's first kernel), then the
+    // Householder tree counters (zero between QRs): kept apart so that flags
+    // a QR leaves behind never land among the counters of a QR of another
+    // shape.
+    int* base = ws.qr_counters(p.nodes + 16, s);
+    int* flags = base;
+    int* cnt = base + 8;
     double* cw = ws.cqws.as<double>(cq_workspace_doubles(m, b));
     launch_cq(a, m, b, lda, r_out, cw, flags, s, ws.lazy_qr ? ws.qr_sticky : nullptr);
     if (!ws.lazy_qr) {

@@ -131,6 +131,27 @@ def test_qr_second_pass_both_factor_paths(lib, cond):
     assert np.max(np.abs(q - ref)) < 1e-15 * cond * 100
 
 
+def test_qr_fallback_after_qrs_of_other_shapes(lib):
+    """Route flags that a QR leaves in the shared QR scratch (near-identity
+    passes, shifted route, breakdown) must never reach the Householder tree
+    counters of a later QR of another shape: well-conditioned and
+    ill-conditioned 60-column panels of several heights, each followed by
+    rank-deficient panels whose fallback trees have many levels."""
+    import torch
+    rng = np.random.default_rng(12)
+    for m_good, m_bad in [(3840, 6480), (3200, 8000), (5000, 9000), (3840, 3840)]:
+        for cond in (1e2, 1e7):
+            u, _ = np.linalg.qr(rng.standard_normal((m_good, 60)))
+            good = (u * np.geomspace(1.0, 1.0 / cond, 60)[None, :]) @ np.linalg.qr(rng.standard_normal((60, 60)))[0]
+            lib.qr(torch.tensor(good, device="cuda"))
+        bad = rng.standard_normal((m_bad, 12)) @ rng.standard_normal((12, 60))  # rank 12
+        q = lib.qr(torch.tensor(bad, device="cuda")).cpu().numpy()
+        say("qr fallback after", m_good, "->", m_bad)
+        assert np.max(np.abs(q.T @ q - np.eye(60))) < 1e-12
+        p = q[:, :12] @ (q[:, :12].T @ bad)
+        assert np.linalg.norm(bad - p) < 1e-12 * np.linalg.norm(bad)
+
+
 def test_qr_rank_deficient_still_orthonormal(lib):
     import torch
     rng = np.random.default_rng(3)
