@@ -132,8 +132,9 @@ void launch_cq(double* a, int m, int b, int lda, double* r_out, double* ws, int*
 // A (p x q, column-major, lda), p >= q, q <= 64.  On return: G (p x q,
 // ld p) holds A*V with columns sorted by decreasing norm (= U*Sigma), Vs
 // (q x q, ld q) the matching right singular vectors, sig[q] the singular
-// values, and *t_out the kept rank: the smallest t >= 1 whose tail
-// sqrt(sum_{j>=t} sig_j^2) <= tau if tau >= 0, else min(max(target,1), q).
+// values, and t_out[0] the kept rank: the smallest t >= 1 whose tail
+// sqrt(sum_{j>=t} sig_j^2) <= tau if tau >= 0, else min(max(target,1), q)
+// (t_out holds 4 ints: then sweeps and two counters of the split test).
 // trans: A is given transposed, element (i, c) at A[i * lda + c] (a
 // row-major p x q matrix, or the column-major R whose R^T is wanted).
 // split_only (with tau < 0): the caller keeps only the first t = target

@@ -8,7 +8,12 @@
 // reductions, one barrier per round), so a round moves only half of the
 // columns through LDS.
 // One-sided Jacobi gives singular values to high relative accuracy, which
-// the tolerance-based truncation needs.
+// the tolerance-based truncation needs.  A truncation to a fixed rank only
+// needs the best rank-t subspaces, so in that mode sweeping stops as soon
+// as split_certified proves the kept/dropped split (the kept columns are
+// then not diagonalised among themselves).
+// t_out: [0] kept rank, [1] sweeps, [2] Cholesky tests run by the split
+// certificate, [3] pivots those that failed got through.
 #include <algorithm>
 
 #include "kernels.hpp"
