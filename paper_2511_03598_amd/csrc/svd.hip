@@ -79,7 +79,7 @@ constexpr int GLD = 65;  // row stride of the Gram matrix in LDS
 constexpr int CLD = 66;
 
 // Rank-t split certificate for a truncation that only needs the kept
-// subspace.  With B = A V the current columns (stride 64 in As), K the t
+// subspace.  With B = A V the current columns (stride CLD in As), K the t
 // columns of largest norm and D the rest, the truncation B_K V_K^T is the
 // best rank-t approximation of A up to sin(theta) ||A|| once
 //   sin(theta) <= ||B_K^T B_D||_F / (lambda_min(B_K^T B_K) - lambda_max(B_D^T B_D)) <= 1e-13
@@ -88,8 +88,9 @@ constexpr int CLD = 66;
 // off-diagonal part (Weyl); lambda_min of the K block > mu, mu = that
 // bound + ||G_KD||_F / 1e-13 + a rounding margin, when its smallest diagonal
 // entry minus the Frobenius norm of its off-diagonal part exceeds mu
-// (Weyl), else when the Cholesky of G_KK - mu I keeps every pivot positive.  Columns are ranked by the
-// same squared norms (16-lane sums) and rule as the final sort, so K is
+// (Weyl), else when the Cholesky of G_KK - mu I keeps every pivot
+// positive.  Columns are ranked by the same squared norms (16-lane sums)
+// and rule as the final sort, so K is
 // exactly the set the caller keeps.  The Gram matrix comes from MFMA in
 // rank order (eight waves, the ten 16x16 tiles on and above the diagonal),
 // so K is its leading t x t block.  Returns true when certified; uniform
@@ -136,9 +137,8 @@ __device__ bool split_certified(const double* As, int q, int t, double* Gs, doub
             const int I = tile_i(e), J = tile_j(e);
             const double* ca = As + ord[I * 16 + li] * LD + lg;
             const double* cb = As + ord[J * 16 + li] * LD + lg;
-            // two accumulators (k0 = 0, 8, ... and 4, 12, ...) halve the
-            // dependent MFMA chain
-            // dependent MFMA chain; all operands are loaded first
+            // all operands are loaded first; two accumulators (even and odd
+            // k-steps) halve the dependent MFMA chain
             double av[16], bv[16];
 #pragma unroll
             for (int k = 0; k < 16; ++k) {
