@@ -68,6 +68,26 @@ def test_server_results_same_alone_and_in_mix(lib):
         assert info["done_s"] >= info["start_s"] >= info["submit_s"]
 
 
+def test_server_fixed_truncation_concurrent_equals_direct(lib):
+    """Fixed-rank roundings with a truncation (sketch ell = 12, target 10)
+    served concurrently by four workers give bitwise the direct call's
+    result (QR scratch, truncation buffers and SVD state are per
+    workspace)."""
+    x = ttgen.c1()
+    dv = to_dev(x)
+    tgt = [1] + [10] * 5 + [1]
+    y1, i1 = lib.round_fixed(dv, 12, 42, target_ranks=tgt)
+    srv = lib.Server(workers=4)
+    try:
+        tickets = [srv.submit(dv, kind="fixed", ell=12, target_ranks=tgt, seed=42) for _ in range(12)]
+        got = [srv.wait(t) for t in tickets]
+    finally:
+        srv.close()
+    for ys, info in got:
+        assert info["ranks"] == i1["ranks"] == tgt
+        assert _same(to_host(ys), to_host(y1))
+
+
 def test_server_budget_serialises_and_rejects(lib):
     xs = _mix(3, 500)
     devs = [to_dev(x) for x in xs]
