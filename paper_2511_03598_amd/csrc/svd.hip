@@ -389,28 +389,47 @@ __global__ void __launch_bounds__(512) svd_jacobi_kernel(const double* A, int ld
                 break;
         }
     }
-    // Column norms, sort by decreasing norm (stable by index).
+    // Column norms; order by decreasing squared norm, ties by index (the
+    // order split_certified uses): thread (column tid/8, part tid%8) counts
+    // the larger norms among columns part + 8u, summed over its 8 lanes.
     for (int c = g8; c < q; c += 32) {
         double s = 0.0;
         for (int i = l8; i < 64; i += 16) s += As[c * LD + i] * As[c * LD + i];
         s = group16_sum(s);
-        if (l8 == 0) sg[c] = ldexp(sqrt(s), sexp);
+        if (l8 == 0) {
+            nd[c] = s;
+            sg[c] = ldexp(sqrt(s), sexp);
+        }
     }
     __syncthreads();
-    if (tid < q) {
-        int rank = 0;
-        const double me = sg[tid];
-        for (int i = 0; i < q; ++i) rank += (sg[i] > me) || (sg[i] == me && i < tid);
-        perm[rank] = tid;
+    {
+        const int c = tid >> 3, part = tid & 7;
+        const double me = c < q ? nd[c] : 0.0;
+        int cnt = 0;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int i = part + 8 * u;
+            if (i < q) {
+                const double o = nd[i];
+                cnt += (o > me) || (o == me && i < c);
+            }
+        }
+        cnt += __builtin_amdgcn_mov_dpp(cnt, 0xB1, 0xF, 0xF, true);   // quad_perm [1,0,3,2]
+        cnt += __builtin_amdgcn_mov_dpp(cnt, 0x4E, 0xF, 0xF, true);   // quad_perm [2,3,0,1]
+        cnt += __builtin_amdgcn_mov_dpp(cnt, 0x141, 0xF, 0xF, true);  // row_half_mirror
+        if (part == 0) perm[c] = c;  // a valid column in every slot even if a NaN norm broke the ranking
+        __syncthreads();
+        if (part == 0 && c < q) perm[cnt] = c;
     }
     __syncthreads();
-    for (int t = tid; t < p * q; t += 512) {
-        const int r = t / p, i = t - r * p;
-        G[(size_t)r * p + i] = ldexp(As[perm[r] * LD + i], sexp);
-    }
-    for (int t = tid; t < q * q; t += 512) {
-        const int r = t / q, i = t - r * q;
-        Vs[(size_t)r * q + i] = V[perm[r] * LD + i];
+    // column r of G and Vs from column perm[r]: thread (r = tid/8, rows tid%8 + 8u)
+    {
+        const int r = tid >> 3, i0 = tid & 7;
+        if (r < q) {
+            const int pc = perm[r];
+            for (int i = i0; i < p; i += 8) G[(size_t)r * p + i] = ldexp(As[pc * LD + i], sexp);
+            for (int i = i0; i < q; i += 8) Vs[(size_t)r * q + i] = V[pc * LD + i];
+        }
     }
     if (tid < q) sig[tid] = sg[perm[tid]];
     if (tid == 0) {
