@@ -532,10 +532,23 @@ __global__ void __launch_bounds__(256) cq_rout_kernel(CqDev q) {
     const int lane = tid & 63, w = tid >> 6, li = lane & 15, lg = lane >> 4;
     __shared__ double A[64 * LDT];
     __shared__ double B[64 * LDT];
-    for (int t = tid; t < 64 * 64; t += 256) A[(t >> 6) * LDT + (t & 63)] = q.rfac[t];
+    // all loads of a matrix are issued before its LDS stores
+    double ra[16];
+#pragma unroll
+    for (int e = 0; e < 16; ++e) ra[e] = q.rfac[tid + 256 * e];
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+        const int t = tid + 256 * e;
+        A[(t >> 6) * LDT + (t & 63)] = ra[e];
+    }
     for (int p = 1; p < npass; ++p) {
-        for (int t = tid; t < 64 * 64; t += 256)
-            B[(t >> 6) * LDT + (t & 63)] = q.rfac[(size_t)p * 4096 + t];
+#pragma unroll
+        for (int e = 0; e < 16; ++e) ra[e] = q.rfac[(size_t)p * 4096 + tid + 256 * e];
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+            const int t = tid + 256 * e;
+            B[(t >> 6) * LDT + (t & 63)] = ra[e];
+        }
         __syncthreads();
         // C = B A
         double4_t acc[4];
@@ -556,9 +569,11 @@ __global__ void __launch_bounds__(256) cq_rout_kernel(CqDev q) {
                 A[(w * 16 + mfma_row_f64(lg, v)) * LDT + nb * 16 + li] = acc[nb][v];
         __syncthreads();
     }
-    for (int t = tid; t < b * b; t += 256) {
-        const int col = t / b, i = t - col * b;
-        q.r_out[t] = (i <= col) ? A[i * LDT + col] : 0.0;
+    // column-major b x b: thread (column tid/4, rows tid%4 + 4u)
+    {
+        const int col = tid >> 2;
+        if (col < b)
+            for (int i = tid & 3; i < b; i += 4) q.r_out[(size_t)col * b + i] = (i <= col) ? A[i * LDT + col] : 0.0;
     }
 }
 
