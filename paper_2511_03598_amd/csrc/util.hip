@@ -35,18 +35,26 @@ __global__ void __launch_bounds__(256) sumsq_kernel(const double* __restrict__ a
     __shared__ int last;
     const int64_t total = (int64_t)rows * cols;
     double s = 0.0;
-    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
-         t += (int64_t)gridDim.x * blockDim.x) {
-        int r, c;
-        if (sr == 1) {
-            c = (int)(t / rows);
-            r = (int)(t - (int64_t)c * rows);
-        } else {
-            r = (int)(t / cols);
-            c = (int)(t - (int64_t)r * cols);
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    if ((sr == 1 && sc == rows) || (sc == 1 && sr == cols)) {
+        // contiguous (the estimator's residual block): no index arithmetic
+        for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += stride) {
+            const double v = a[t];
+            s += v * v;
         }
-        const double v = a[(size_t)r * sr + (size_t)c * sc];
-        s += v * v;
+    } else {
+        for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += stride) {
+            int r, c;
+            if (sr == 1) {
+                c = (int)(t / rows);
+                r = (int)(t - (int64_t)c * rows);
+            } else {
+                r = (int)(t / cols);
+                c = (int)(t - (int64_t)r * cols);
+            }
+            const double v = a[(size_t)r * sr + (size_t)c * sc];
+            s += v * v;
+        }
     }
     s = block_sum256(s, red);
     if (threadIdx.x == 0) {
