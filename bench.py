@@ -100,6 +100,9 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-parity", action="store_true")
+    ap.add_argument("--no-concurrent", action="store_true",
+                    help="skip the served-concurrency figure (profiling runs: it would mix "
+                         "concurrent kernels into the per-kernel statistics)")
     ap.add_argument("--workload", choices=["c2", "c4", "c5", "sum", "precision"], default="c2",
                     help="c2 (default): the fixed-rank rounding the metric is quoted on; "
                          "c4: batched adaptive rounding vs a plain loop; c5: served rounding "
@@ -220,21 +223,25 @@ def main():
     # SVDs and QR factorisations each run on one CU), so the same rounding
     # is also submitted 32 times to the library's server (8 workers, one HIP
     # stream each).  Reported beside `value`, which stays the one-stream rate.
-    srv = ttr.Server(workers=8)
+    if args.no_concurrent:
+        srv = None
+    else:
+        srv = ttr.Server(workers=8)
     def submit():
         return srv.submit(dev, kind="fixed", ell=ELL, target_ranks=tgt, seed=SEED, prec="f32")
-    for t in [submit() for _ in range(8)]:
-        srv.wait(t)
-    nreq = 32
-    t0 = time.perf_counter()
-    tks = [submit() for _ in range(nreq)]
-    served = [srv.wait(t) for t in tks]
-    conc_s = time.perf_counter() - t0
-    srv.close()
-    out["concurrent"] = {
-        "roundings_per_s": nreq / conc_s, "requests": nreq, "workers": 8,
-        "bitwise_equal_to_one_stream": all(torch.equal(u, v) for u, v in zip(served[-1][0], y)),
-    }
+    if srv is not None:
+        for t in [submit() for _ in range(8)]:
+            srv.wait(t)
+        nreq = 32
+        t0 = time.perf_counter()
+        tks = [submit() for _ in range(nreq)]
+        served = [srv.wait(t) for t in tks]
+        conc_s = time.perf_counter() - t0
+        srv.close()
+        out["concurrent"] = {
+            "roundings_per_s": nreq / conc_s, "requests": nreq, "workers": 8,
+            "bitwise_equal_to_one_stream": all(torch.equal(u, v) for u, v in zip(served[-1][0], y)),
+        }
     if not args.no_parity:
         from oracle import krp, tt
         yo, io = krp.round_fixed(x, ELL, SEED, tgt)
