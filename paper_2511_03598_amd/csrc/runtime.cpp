@@ -871,7 +871,15 @@ static bool round_adaptive_once(Workspace& ws, const Summands& x, double tol, in
             info.iterations++;
             if (tau > 0) info.min_margin = std::min(info.min_margin, std::fabs(est - tau) / tau);
             if (!(est > tau)) break;
-            qr(ws, st, S, rows, bb, rows);
+            {
+                // The residual block is where a sketch wider than the numerical
+                // rank shows up: its QR keeps the eager fallback, so such a
+                // breakdown costs no repeat of the rounding.
+                const bool lazy = ws.lazy_qr;
+                ws.lazy_qr = false;
+                qr(ws, st, S, rows, bb, rows);
+                ws.lazy_qr = lazy;
+            }
             gemm(ws, st, ncq, bb, rows, Q, rows, 1, S, 1, rows, T, bb, 1);
             gemm(ws, st, rows, bb, ncq, Q, 1, rows, T, bb, 1, S, 1, rows, -1.0, 1.0);
             qr(ws, st, S, rows, bb, rows);
