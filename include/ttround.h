@@ -220,9 +220,15 @@ tt_status tt_round_adaptive_batch(const tt_view* xs, int32_t count, const double
  * A server owns worker threads (one HIP stream each) on the device current
  * at creation.  Requests queue in arrival order and start as soon as a
  * worker is free and their device-memory footprint (tt_workspace_bytes plus
- * twice the output capacity) fits the budget beside the running requests
- * and the results not yet released; a request that fits may start before
- * an earlier one that does not (at most four times per waiting request).
+ * four times the output capacity: capacity-sized staging and the exact-size
+ * result, each from power-of-two pool classes) fits the budget beside the
+ * running requests and the results not yet released; a request that fits
+ * may start before an earlier one that does not (at most four times per
+ * waiting request).  The budget counts request footprints only: the
+ * workspaces and pool buffers the library caches for reuse between requests
+ * (at most one workspace per worker thread, grown to the largest request it
+ * ran) are not counted, so leave headroom for them below the device's free
+ * memory.
  * New requests are admitted while others run, and their kernels overlap on
  * the device.  Each result is bitwise the same as the synchronous call with
  * the same arguments. */

@@ -174,6 +174,21 @@ def norm_estimate(core1, w2):
     return float(np.linalg.norm(v_unf(core1) @ w2) / math.sqrt(w2.shape[1]))
 
 
+def initial_sketch_columns(cores, f_init):
+    """Sec. 3.3, first step of the adaptive algorithm: the Gaussian factors
+    start with r = ceil(f_init * max_j r_j) columns, the maximum taken over
+    the interior ranks r_1 .. r_{d-1} of X."""
+    rmax = max(c.shape[2] for c in cores[:-1])
+    return int(math.ceil(f_init * rmax))
+
+
+def modewise_threshold(tol, nrmx, d):
+    """Sec. 3.3: the accuracy eps is spread evenly over the d-1 bonds, so
+    each mode's residual must fall below tau = eps * ||X|| / sqrt(d-1)
+    (the allocation the paper justifies with its Theorem 8.6 reference)."""
+    return tol * nrmx / math.sqrt(d - 1)
+
+
 def round_adaptive(cores, tol, ell_block, seed, nrmx=None, f_init=0.1,
                    recompress=0, keep=False):
     """Adaptive-rank Rand-Orth-KRP (Sec. 3.3) with residual sketching.
@@ -182,12 +197,11 @@ def round_adaptive(cores, tol, ell_block, seed, nrmx=None, f_init=0.1,
     is 1 (Remark 2 pass with the same tau), then right-orthonormal.
     """
     d = len(cores)
-    rmax = max(c.shape[2] for c in cores[:-1])
-    r0 = int(math.ceil(f_init * rmax))
+    r0 = initial_sketch_columns(cores, f_init)
     sk = _Sketches(cores, seed, r0)
     if nrmx is None or nrmx <= 0:
         nrmx = norm_estimate(cores[0], sk.w[2])
-    tau = tol * nrmx / math.sqrt(d - 1)
+    tau = modewise_threshold(tol, nrmx, d)
     ys = [None] * d
     y = np.array(cores[0], copy=True)
     ests, margins, kept = [], [], []

@@ -30,6 +30,13 @@ def truncation_rank(s, tau):
     return m
 
 
+def bond_threshold(tol, norm, d):
+    """Algorithm TT-Rounding (Sec. 2.3): tau = ||Y|| eps / sqrt(d-1), so
+    that d-1 truncations of tail at most tau keep the total error within
+    eps ||Y||."""
+    return tol * norm / math.sqrt(d - 1)
+
+
 def tt_svd_round(cores, tol=None, ranks=None):
     """Round X by TT-SVD.  Give tol (relative accuracy) or ranks (list of
     d+1 target ranks, ends 1).  Returns (cores, info)."""
@@ -38,7 +45,7 @@ def tt_svd_round(cores, tol=None, ranks=None):
     ys = orthogonalize_rl(cores)
     d = len(ys)
     nrm = float(np.linalg.norm(ys[0]))
-    tau = tol * nrm / math.sqrt(d - 1) if tol is not None else None
+    tau = bond_threshold(tol, nrm, d) if tol is not None else None
     svals = []
     for k in range(d - 1):
         r0, n, _ = ys[k].shape

@@ -211,6 +211,13 @@ void Executor::run(Job& j, hipStream_t st) {
         j.status = -4;
         j.error = e.what();
     }
+    // On an error kernels may still be queued that write the staging or
+    // result buffers: drain the stream before they return to the pool, where
+    // a rounding on another worker's stream could take them.
+    if (j.status != 0) {
+        (void)hipStreamSynchronize(st);
+        (void)hipGetLastError();
+    }
     for (size_t k = 0; k < cap_bufs.size(); ++k) pool_.free(cap_bufs[k], cap_rounded[k]);
     if (j.status != 0 && j.owned_output) {
         for (size_t k = 0; k < j.out_cores.size(); ++k)

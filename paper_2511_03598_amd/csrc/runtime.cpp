@@ -18,6 +18,7 @@
 #include <climits>
 #include <cstdio>
 #include <cstdlib>
+#include <exception>
 #include <memory>
 #include <mutex>
 
@@ -107,9 +108,16 @@ struct Workspace {
 std::mutex g_pool_mu;
 std::vector<std::unique_ptr<Workspace>> g_pool;
 
+// A workspace taken from the pool for one call.  `stream` is the stream the
+// call enqueues on: if an error unwinds past the lease after kernels were
+// queued, the stream is drained before the workspace goes back to the pool,
+// so no other call (on another stream) can take buffers that queued kernels
+// still read or write.
 struct WsLease {
     std::unique_ptr<Workspace> ws;
-    WsLease() {
+    hipStream_t stream;
+    int unwinding_at_entry;
+    explicit WsLease(hipStream_t s) : stream(s), unwinding_at_entry(std::uncaught_exceptions()) {
         int dev = 0;
         TTR_HIP(hipGetDevice(&dev));
         {
@@ -126,6 +134,12 @@ struct WsLease {
     }
     ~WsLease() {
         if (ws) {
+            if (std::uncaught_exceptions() > unwinding_at_entry) {
+                // an error on the way out: wait for what was queued (and clear
+                // a sticky error so the next call does not report it)
+                (void)hipStreamSynchronize(stream);
+                (void)hipGetLastError();
+            }
             std::lock_guard<std::mutex> lk(g_pool_mu);
             g_pool.push_back(std::move(ws));
         }
@@ -513,6 +527,10 @@ void next_core(Workspace& ws, hipStream_t st, const Summands& x, int k, const do
 void recompress(Workspace& ws, hipStream_t st, const Shape& s, double** cores, int64_t* ranks,
                 double tau, const int64_t* target) {
     const int d = s.d;
+    // every step factors a core whose left rank is an untruncated bond rank:
+    // reject before anything of the pass is queued
+    for (int k = 1; k < d; ++k)
+        if (ranks[k] > 64) throw Error(-6, "recompression supports ranks <= 64");
     int64_t maxcore = 0;
     for (int k = 1; k <= d; ++k) maxcore = std::max(maxcore, ranks[k - 1] * s.n[k - 1] * ranks[k]);
     double* buf[2] = {ws.y0.as<double>(maxcore + 64), ws.y1.as<double>(maxcore + 64)};
@@ -523,7 +541,6 @@ void recompress(Workspace& ws, hipStream_t st, const Shape& s, double** cores, i
         const int b = (int)ranks[k - 1];
         const int m = (int)(s.n[k - 1] * ranks[k]);
         double* H = buf[cb];  // b x m row-major
-        if (b > 64) throw Error(-6, "recompression supports ranks <= 64");
         double* G = ws.small2.as<double>((size_t)b * b + 64);
         double* Vs = ws.small3.as<double>((size_t)b * b + 64);
         double* sig = ws.small4.as<double>(b + 64);
@@ -767,7 +784,7 @@ void round_fixed(const Summands& x, const int64_t* target, int64_t ell, uint64_t
                  const Options& o, OutCores& y, RoundInfo& info) {
     if (ell < 1) throw Error(-1, "ell must be >= 1");
     if (ell > 64) throw Error(-6, "fixed-rank sketch size ell > 64 is not supported");
-    WsLease lease;
+    WsLease lease(o.stream);
     const bool force = force_qr_retry();
     for (int attempt = 0; attempt < 2; ++attempt) {
         LazyQr lq(*lease.ws, o.stream, attempt == 0);
@@ -911,7 +928,7 @@ static bool round_adaptive_once(Workspace& ws, const Summands& x, double tol, in
 void round_adaptive(const Summands& x, double tol, int64_t ell_block, uint64_t seed,
                     const Options& o, OutCores& y, RoundInfo& info) {
     if (!(tol > 0.0)) throw Error(-1, "tol must be > 0");
-    WsLease lease;
+    WsLease lease(o.stream);
     const bool force = force_qr_retry();
     for (int attempt = 0; attempt < 2; ++attempt) {
         LazyQr lq(*lease.ws, o.stream, attempt == 0);
@@ -933,7 +950,7 @@ void round_adaptive(const Shape& s, const double* const* cores, double tol, int6
 void gaussian_factor(uint64_t seed, int mode, int64_t n, int64_t col0, int64_t ncols, double* out,
                      hipStream_t st) {
     if (mode < 1 || n < 1 || ncols < 0 || col0 < 0 || !out) throw Error(-1, "bad Omega request");
-    WsLease lease;
+    WsLease lease(st);
     int64_t* dn = lease->dn.as<int64_t>(2);
     int64_t* doff = lease->doff.as<int64_t>(2);
     const int64_t hn[2] = {n, 0}, ho[2] = {0, 0};
@@ -958,7 +975,7 @@ void partial_contractions(const Shape& s, const double* const* cores, uint64_t s
     if (t < 2 || t > s.d) throw Error(-1, "t must be in [2, d]");
     if (ncols < 1 || col0 < 0) throw Error(-1, "bad column range");
     if (prec < 0 || prec > 2) throw Error(-6, "precision not supported for partial contractions");
-    WsLease lease;
+    WsLease lease(st);
     Workspace& ws = *lease.ws;
     const Summands x = single_term(s, cores);
     Sketch sk(x, seed, prec, ncols, st, ws, col0);
@@ -972,7 +989,7 @@ void partial_contractions(const Shape& s, const double* const* cores, uint64_t s
 void qr_inplace(double* a, int64_t m, int64_t b, hipStream_t st) {
     if (!a || m < 1 || b < 1) throw Error(-1, "bad QR request");
     if (m < b) throw Error(-1, "QR needs m >= b");
-    WsLease lease;
+    WsLease lease(st);
     qr(*lease.ws, st, a, (int)m, (int)b, (int)m);
     TTR_HIP(hipStreamSynchronize(st));
 }
@@ -980,7 +997,7 @@ void qr_inplace(double* a, int64_t m, int64_t b, hipStream_t st) {
 int64_t svd_small(const double* a, int64_t p, int64_t q, double* g, double* v, double* sig,
                   double tau, int64_t target, hipStream_t st) {
     if (!a || !g || !v || !sig || q < 1 || q > 64 || p < q) throw Error(-1, "bad SVD request");
-    WsLease lease;
+    WsLease lease(st);
     int* tdev = lease->tint.as<int>(16);
     {
         TimedScope ts(KT_SVD, st);

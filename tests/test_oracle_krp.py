@@ -240,3 +240,78 @@ def test_adaptive_recompress_matches_ttsvd_ranks_c1():
     assert info["ranks"] == sinfo["ranks"] == [1, 10, 10, 10, 10, 10, 1]
     assert tt.rel_err(x, y) < 1e-13
     assert tt.right_orth_defect(y) < 1e-13
+
+
+def _orthogonal_rank_one_sum(rng, d, n, sig):
+    """X = sum_j sig_j u_1^(j) (x) ... (x) u_d^(j) with the u_k^(j), j = 1..r,
+    orthonormal in every mode k.  The left factors u_1^(j) (x) ... (x)
+    u_k^(j) of any unfolding X_(1:k) are then orthonormal, and so are the
+    right ones, so every bond's singular values are exactly sig (a closed
+    form).  As a TT: first core U_1 diag(sig), diagonal middle cores
+    X_k(j, :, j) = u_k^(j), last core U_d^T; all ranks r."""
+    r = len(sig)
+    us = [np.linalg.qr(rng.standard_normal((n, r)))[0] for _ in range(d)]
+    cores = [(us[0] * np.asarray(sig)[None, :]).reshape(1, n, r)]
+    for k in range(1, d - 1):
+        c = np.zeros((r, n, r))
+        for j in range(r):
+            c[j, :, j] = us[k][:, j]
+        cores.append(c)
+    cores.append(np.ascontiguousarray(us[d - 1].T).reshape(r, n, 1))
+    return cores
+
+
+def test_orthogonal_rank_one_sum_has_known_bond_spectra():
+    """The construction above, checked by brute force: the SVD of every
+    dense unfolding is sig."""
+    sig = np.array([1.0, 0.3, 0.05, 2e-3, 1e-4])
+    x = _orthogonal_rank_one_sum(ttgen.rng_for(95), 4, 6, sig)
+    f = tt.full(x)
+    for k in range(1, 4):
+        s = np.linalg.svd(f.reshape(6 ** k, -1), compute_uv=False)
+        assert np.allclose(s[:5], sig, rtol=1e-12, atol=1e-14)
+        assert np.all(s[5:] < 1e-13)
+
+
+# d = 5 (so sqrt(d-1) = 2) with bond spectra 10^-(j-1), j = 1..8, and
+# eps = 1.5e-3.  By hand: ||X|| = 1.00504, tau = eps ||X|| / 2 = 7.54e-4;
+# the tails sqrt(sum_{j>t} sig_j^2) are 1.005e-3 at t = 3 (> tau) and
+# 1.005e-4 at t = 4 (<= tau), so every bond keeps 4 terms.  The undivided
+# threshold eps ||X|| = 1.51e-3 would already accept t = 3.
+_SIG_D5 = 10.0 ** -np.arange(8)
+_EPS_D5 = 1.5e-3
+_RANKS_D5 = [1, 4, 4, 4, 4, 1]
+
+
+def test_adaptive_threshold_spreads_tolerance_over_bonds():
+    """Sec. 3.3: tau = eps ||X|| / sqrt(d-1).  With blocks as wide as the
+    ranks the sweep captures X exactly (sketch ranks 8), so the Remark 2
+    pass truncates the exact spectra with the tail rule at tau: the ranks
+    must be the hand-computed ones above, and TT-SVD (Sec. 2.3) must land
+    on the same ranks."""
+    x = _orthogonal_rank_one_sum(ttgen.rng_for(96), 5, 10, _SIG_D5)
+    nrm = math.sqrt(float(np.sum(_SIG_D5 ** 2)))
+    y, info = krp.round_adaptive(x, _EPS_D5, ell_block=8, seed=3, nrmx=nrm, recompress=1)
+    assert info["sketch_ranks"] == [1, 8, 8, 8, 8, 1]
+    assert info["ranks"] == _RANKS_D5
+    assert tt.rel_err(x, y) <= _EPS_D5
+    ys, sinfo = ttsvd.tt_svd_round(x, tol=_EPS_D5)
+    assert sinfo["ranks"] == _RANKS_D5
+
+
+def test_initial_sketch_uses_largest_rank():
+    """Sec. 3.3 (first step of the adaptive algorithm) and Remark 1: the
+    Gaussian factors start with r = ceil(f_init max_j r_j) columns and the
+    norm estimate uses all of them.  Ranks (1, 6, 23, 6, 1): by hand
+    r = ceil(0.1 * 23) = 3 (the smallest rank would give 1).  The estimate
+    must equal ||V(X_1) W_2||_F / sqrt(3) with W_2's three columns formed
+    from the definition (explicit suffix unfolding times explicit KRP)."""
+    dims = [6, 8, 8, 6]
+    x = ttgen.small_random(97, 4, dims, [6, 23, 6])
+    assert tt.ranks_of(x) == [1, 6, 23, 6, 1]
+    y, info = krp.round_adaptive(x, 1e-3, 4, seed=5)
+    assert info["r0"] == 3
+    oms = [philox.gaussian_factor(5, j, dims[j - 1], 0, 3) for j in range(2, 5)]
+    w2 = _suffix_h(x, 2) @ _explicit_krp(oms)
+    est = np.linalg.norm(x[0].reshape(6, 6) @ w2) / math.sqrt(3)
+    assert info["nrmx"] == pytest.approx(est, rel=1e-12)

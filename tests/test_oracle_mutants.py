@@ -138,3 +138,25 @@ def test_sum_weight_applied_twice_caught(monkeypatch):
 
     monkeypatch.setattr(tt, "formal_sum", wrong)
     _fails(pins_sum.test_sum_fixed_d2_is_range_finder_of_weighted_sum)
+
+
+def test_threshold_without_sqrt_d_minus_1_caught(monkeypatch):
+    """The whole accuracy given to every bond instead of eps/sqrt(d-1)."""
+    monkeypatch.setattr(krp, "modewise_threshold", lambda tol, nrmx, d: tol * nrmx)
+    _fails(pins_krp.test_adaptive_threshold_spreads_tolerance_over_bonds)
+
+
+def test_ttsvd_threshold_without_sqrt_d_minus_1_caught(monkeypatch):
+    monkeypatch.setattr(ttsvd, "bond_threshold", lambda tol, norm, d: tol * norm)
+    _fails(pins_krp.test_adaptive_threshold_spreads_tolerance_over_bonds)
+
+
+def test_initial_sketch_from_smallest_rank_caught(monkeypatch):
+    """r0 from the smallest interior rank instead of the largest."""
+    import math
+
+    def wrong(cores, f_init):
+        return int(math.ceil(f_init * min(c.shape[2] for c in cores[:-1])))
+
+    monkeypatch.setattr(krp, "initial_sketch_columns", wrong)
+    _fails(pins_krp.test_initial_sketch_uses_largest_rank)
