@@ -1,21 +1,33 @@
 #!/usr/bin/env python
-"""Benchmark: KRP-sketched TT-rounding on one MI355X.
+"""Benchmark: KRP-sketched adaptive TT-rounding on one MI355X.
 
-Workload (the configuration the metric is quoted on): fixed-rank
-randomize-then-orthogonalize rounding with KRP sketches of
-X = sum of 4 random TTs (d=20, n=64, ranks 50, N(0,1) cores) weighted
-(1, 1e-2, 1e-4, 1e-6): formal ranks 200, sketch size ell=60, truncated to
-target ranks 50.  Partial contractions (the sketch) in FP32 with FP32
-accumulation; sketch GEMM, QR, projection, next core and truncation in FP64.
+Headline workload (default): the batch of 256 independent TT tensors (d
+uniform in [4,16], n in [16,128], formal ranks in [8,128]; each a sum of 3
+N(0,1) TTs weighted 1, 1e-4, 1e-8) rounded adaptively to tol 1e-6 with
+blocks of 16 sketch columns, all in FP64, through the batch entry point.
+A step is one rounding of the whole batch (every hot-path step of every
+tensor), inputs resident in HBM; `value` is tensors rounded per second over
+the timed steps.  Printed beside it, in one JSON line:
 
-A step is one whole rounding of X (all hot-path steps), inputs resident in
-HBM.  Prints one JSON line.  Also reported:
-  * sketch GB/s and the roofline of the partial-contraction kernel
-    (algorithmic bytes per launch / average launch duration, from HIP event
-    pairs that the library records on this stream around every launch of
-    that kernel during the timed steps);
-  * the CPU oracle on the host cores (a bounded sample of full roundings);
-  * parity of the last result against the oracle (relative to ||X||).
+  * the plain single-instance rate (one tt_round_adaptive call after the
+    other on one stream, same tensors and seeds, bitwise the same results);
+  * median / p10 / p90 of the step times;
+  * sketch GB/s: the partial contractions' algorithmic bytes (one FP64
+    read of each contracted core plus the W writes, every pass including
+    the regeneration passes) over the batch's wall time;
+  * `roofline`: the partial-contraction kernel inside the timed steps --
+    algorithmic bytes (or flops) per launch over the average launch
+    duration, from HIP event pairs the library records on each launch
+    stream around its back-to-back partial-contraction launches;
+  * the same kernel at the two sizes where it is a large launch: the
+    fixed-rank C2 rounding with an FP32 sketch (HBM-bound) and the adaptive
+    C3 rounding with an FP64 sketch (FP64-MFMA-bound), with their rates;
+  * parity of sampled tensors against the CPU oracle and their error
+    against X;
+  * `cpu_baseline`: the CPU oracle's KRP rounding (and its TT-SVD rounding)
+    of a systematic sample of the batch on the host cores, with the thread
+    count, and single-threaded.
+Other workloads: --workload c2 | c5 | sum | precision.
 """
 import argparse
 import json
@@ -28,19 +40,29 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0
+FP64_MFMA_PEAK_TFLOPS = 78.6
+FP32_MFMA_PEAK_TFLOPS = 157.3
 D, N, R, TERMS, ELL, TARGET, SEED = 20, 64, 50, 4, 60, 50, 42
+C4_TOL, C4_BLOCK = 1e-6, 16
+C3_TOL, C3_BLOCK, C3_SEED = 1e-6, 16, 42
 
 
-def workload_desc():
+def c2_desc():
     return ("fixed-rank KRP TT-rounding, X = sum of 4 random TTs (d=20, n=64, ranks 50, "
             "weights 1,1e-2,1e-4,1e-6; formal ranks 200), ell=60 -> target ranks 50, "
             "FP32 sketch + FP64 QR")
 
 
+def c4_desc(count):
+    return ("adaptive KRP TT-rounding of a batch of %d TTs (d in [4,16], n in [16,128], formal "
+            "ranks in [8,128]; sums of 3 N(0,1) TTs weighted 1,1e-4,1e-8), tol 1e-6, ell blocks "
+            "of 16, FP64, one batch call per step" % count)
+
+
 def sketch_bytes(dims, ranks, ell, w_bytes):
-    """Algorithmic bytes of one right-to-left partial-contraction pass:
-    one FP64 read of cores 2..d plus the W_k writes (Omega, W reads are
-    negligible and not counted)."""
+    """Algorithmic bytes of one right-to-left partial-contraction pass over
+    all of cores 2..d with ell columns: one FP64 read of the cores plus the
+    W_k writes (Omega and W reads are negligible and not counted)."""
     d = len(dims)
     core = sum(ranks[k - 1] * dims[k - 1] * ranks[k] * 8 for k in range(2, d + 1))
     wout = sum(ranks[k - 1] * ell * w_bytes for k in range(2, d + 1))
@@ -51,14 +73,14 @@ PMC_SUMMARY = os.path.join(ROOT, "profiles", "pc_kernel_c2_pmc.txt")
 PC_SOURCE = os.path.join(ROOT, "paper_2511_03598_amd", "csrc", "partial.hip")
 
 
-def pmc_traffic(alg_bytes_per_launch):
-    """HBM bytes per partial-contraction launch from the committed rocprofv3
+def pmc_traffic(path, alg_bytes_per_launch):
+    """HBM bytes per partial-contraction launch from a committed rocprofv3
     FETCH_SIZE / WRITE_SIZE summary, or None when there is none or the
     kernel source changed since it was taken (the summary records the
     source's sha256)."""
     import hashlib
     try:
-        text = open(PMC_SUMMARY).read()
+        text = open(path).read()
     except OSError:
         return None
     vals = {}
@@ -72,24 +94,35 @@ def pmc_traffic(alg_bytes_per_launch):
     return float(vals["hbm_bytes_per_launch"])
 
 
-def cpu_baseline(x, budget_s):
-    from oracle import krp
+def roofline(bytes_per_launch, flops_per_launch, avg_launch_s, flop_peak_tflops, kernel, traffic=None):
+    """Roofline entry of one kernel: the bound is the one that gives the
+    longer ideal time (HBM at 8 TB/s or the MFMA peak of its precision)."""
+    t_hbm = bytes_per_launch / (HBM_PEAK_GBPS * 1e9)
+    t_mfma = flops_per_launch / (flop_peak_tflops * 1e12)
+    if t_hbm >= t_mfma:
+        ach = bytes_per_launch / avg_launch_s / 1e9
+        out = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+               "frac": ach / HBM_PEAK_GBPS}
+    else:
+        ach = flops_per_launch / avg_launch_s / 1e12
+        out = {"bound": "mfma", "achieved": ach, "peak": flop_peak_tflops, "unit": "TFLOP/s",
+               "frac": ach / flop_peak_tflops}
+    out.update({"traffic": traffic, "kernel": kernel, "bytes_per_launch": bytes_per_launch,
+                "flops_per_launch": flops_per_launch, "avg_launch_us": avg_launch_s * 1e6})
+    return out
+
+
+def pctl(vals, q):
+    import numpy as np
+    return float(np.percentile(np.asarray(vals, dtype=float), q))
+
+
+def oracle_threads():
     try:
         from threadpoolctl import threadpool_info
-        threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+        return max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
     except Exception:
-        threads = os.cpu_count() or 1
-    tgt = [1] + [TARGET] * (D - 1) + [1]
-    krp.round_fixed(x, ELL, SEED, tgt)  # warm-up
-    n, t0 = 0, time.perf_counter()
-    while True:
-        krp.round_fixed(x, ELL, SEED, tgt)
-        n += 1
-        el = time.perf_counter() - t0
-        if el >= budget_s or n >= 50:
-            break
-    return {"value": n / el, "unit": "TT-roundings/s", "cores": int(threads), "kind": "oracle",
-            "sample": "%d full roundings of the same workload (CPU FP64 NumPy oracle, %.1f s)" % (n, el)}
+        return os.cpu_count() or 1
 
 
 def main():
@@ -97,21 +130,25 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--cpu-budget", type=float, default=15.0,
+                    help="seconds of oracle work per CPU-baseline leg")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-parity", action="store_true")
+    ap.add_argument("--no-side", action="store_true",
+                    help="headline only: skip the C2 and C3 partial-contraction segments")
     ap.add_argument("--no-concurrent", action="store_true",
-                    help="skip the served-concurrency figure (profiling runs: it would mix "
+                    help="c2: skip the served-concurrency figure (profiling runs: it would mix "
                          "concurrent kernels into the per-kernel statistics)")
-    ap.add_argument("--workload", choices=["c2", "c4", "c5", "sum", "precision"], default="c2",
-                    help="c2 (default): the fixed-rank rounding the metric is quoted on; "
-                         "c4: batched adaptive rounding vs a plain loop; c5: served rounding "
+    ap.add_argument("--workload", choices=["c4", "c2", "c5", "sum", "precision"], default="c4",
+                    help="c4 (default): the batch of 256 adaptive roundings at tol 1e-6 (FP64); "
+                         "c2: the fixed-rank rounding with an FP32 sketch; c5: served rounding "
                          "under Poisson arrivals (p50/p99 latency); sum: one large C5 request "
                          "rounded term by term vs the assembled formal sum; precision: adaptive "
                          "rounding of C3 with FP64/FP32/BF16 sketches at tol 1e-4..1e-10")
     ap.add_argument("--count", type=int, default=256, help="c4: tensors in the batch")
-    ap.add_argument("--requests", type=int, default=120, help="c5: requests per arrival rate")
-    ap.add_argument("--workers", type=int, default=8, help="c4/c5: concurrent roundings")
+    ap.add_argument("--plain-reps", type=int, default=3, help="c4: repetitions of the plain loop")
+    ap.add_argument("--requests", type=int, default=500, help="c5: requests per arrival rate")
+    ap.add_argument("--workers", type=int, default=8, help="c5: concurrent roundings")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy three times (the "
                          "reference kernel that scales rocprofv3 FETCH_SIZE/WRITE_SIZE to bytes)")
@@ -121,17 +158,8 @@ def main():
               "describe how it would shard); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
 
-    if args.workload == "c4":
-        return run_c4(args)
-    if args.workload == "c5":
-        return run_c5(args)
-    if args.workload == "sum":
-        return run_sum(args)
-    if args.workload == "precision":
-        return run_precision(args)
     if args.copy_calibration:
         src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")  # 1 GiB
         dst = torch.empty_like(src)
@@ -140,6 +168,254 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_calibration_bytes": src.numel() * 8, "dispatches": 3}), flush=True)
         return
+    if args.workload == "c4":
+        return run_headline(args)
+    if args.workload == "c5":
+        return run_c5(args)
+    if args.workload == "sum":
+        return run_sum(args)
+    if args.workload == "precision":
+        return run_precision(args)
+    return run_c2(args)
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def run_headline(args):
+    import numpy as np
+    import torch
+
+    import paper_2511_03598_amd as ttr
+    import ttgen
+
+    t0 = time.perf_counter()
+    xs = ttgen.c4(count=args.count)
+    devs = [[torch.tensor(c, device="cuda") for c in x] for x in xs]
+    seeds = [42 + t for t in range(len(xs))]
+    log("generated and uploaded %d tensors in %.1f s" % (len(xs), time.perf_counter() - t0))
+
+    def batch():
+        return ttr.round_adaptive_batch(devs, C4_TOL, C4_BLOCK, seeds)
+
+    for _ in range(max(1, args.warmup)):
+        res = batch()
+    torch.cuda.synchronize()
+    log("warm-up done")
+    # timed region: K batch calls (each returns when all its roundings are
+    # complete), with the library's event pairs around the partial
+    # contractions on every worker stream
+    ttr.kernel_timing(True, kinds=["partial_contraction"])
+    step_s = []
+    torch.cuda.synchronize()
+    wall0 = time.perf_counter()
+    for _ in range(args.steps):
+        t1 = time.perf_counter()
+        res = batch()
+        torch.cuda.synchronize()
+        step_s.append(time.perf_counter() - t1)
+    wall = time.perf_counter() - wall0
+    ttr.kernel_timing(False)
+    pc_launches, pc_ms = ttr.kernel_timing_read("partial_contraction")
+    log("timed %d batch steps: median %.3f s" % (args.steps, pctl(step_s, 50)))
+
+    # plain single-instance loop (untimed for `value`); its per-tensor
+    # accounting of the partial contractions is the batch's (same passes)
+    plain_s, plain = [], None
+    for _ in range(max(1, args.plain_reps)):
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        plain = [ttr.round_adaptive(devs[i], C4_TOL, C4_BLOCK, seeds[i]) for i in range(len(devs))]
+        torch.cuda.synchronize()
+        plain_s.append(time.perf_counter() - t1)
+    same = all(p[1]["ranks"] == b[1]["ranks"] and all(torch.equal(u, v) for u, v in zip(p[0], b[0]))
+               for p, b in zip(plain, res))
+    pc_bytes = sum(p[1]["pc_bytes"] for p in plain)
+    pc_flops = sum(p[1]["pc_flops"] for p in plain)
+    pc_per_step = sum(p[1]["pc_launches"] for p in plain)
+    assert pc_launches == pc_per_step * args.steps, (pc_launches, pc_per_step, args.steps)
+    avg_launch_s = pc_ms / 1e3 / pc_launches
+    step_total = sum(step_s)
+    value = len(xs) * args.steps / step_total
+    out = {
+        "metric": "TT-roundings/s + sketch GB/s vs plain & TT-SVD at rel err <=1e-6",
+        "value": value,
+        "unit": "TT-roundings/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": step_total / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": c4_desc(len(xs)), "tensors": len(xs), "tol": C4_TOL,
+                   "ell_block": C4_BLOCK, "sketch_precision": "f64",
+                   "input_GB": sum(c.numel() * 8 for x in devs for c in x) / 1e9},
+        "step_s": {"median": pctl(step_s, 50), "p10": pctl(step_s, 10), "p90": pctl(step_s, 90),
+                   "steps": args.steps},
+        "plain_value": len(xs) / pctl(plain_s, 50),
+        "plain_step_s": {"median": pctl(plain_s, 50), "reps": len(plain_s)},
+        "speedup_vs_plain": pctl(plain_s, 50) / pctl(step_s, 50),
+        "bitwise_equal_to_plain": same,
+        "sketch_GBps": pc_bytes * args.steps / step_total / 1e9,
+        "roofline": roofline(pc_bytes / pc_per_step, pc_flops / pc_per_step, avg_launch_s,
+                             FP64_MFMA_PEAK_TFLOPS,
+                             "partial contraction, FP64 (pc_kernel<double>), inside the batch"),
+        "wall_s": wall,
+    }
+    out["roofline"]["launches_per_step"] = pc_per_step
+    if not args.no_side:
+        out["side"] = {"c2_f32": side_c2(args), "c3_f64": side_c3(args)}
+    if not args.no_parity:
+        out["parity"] = c4_parity(xs, res, seeds)
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = c4_cpu_baseline(xs, seeds, args.cpu_budget)
+    print(json.dumps(out), flush=True)
+
+
+def side_c2(args):
+    """The partial contractions of the C2 fixed-rank rounding (FP32 sketch,
+    200-row cores: the HBM-bound launch) and that rounding's rate."""
+    import torch
+
+    import paper_2511_03598_amd as ttr
+    import ttgen
+
+    x = ttgen.c2(d=D, n=N, r=R)
+    dims = [c.shape[1] for c in x]
+    ranks = [1] + [c.shape[2] for c in x]
+    dev = [torch.tensor(c, device="cuda") for c in x]
+    tgt = [1] + [TARGET] * (D - 1) + [1]
+    for _ in range(max(1, args.warmup)):
+        ttr.round_fixed(dev, ELL, SEED, target_ranks=tgt, prec="f32")
+    torch.cuda.synchronize()
+    ttr.kernel_timing(True, kinds=["partial_contraction"])
+    times = []
+    for _ in range(args.steps):
+        t1 = time.perf_counter()
+        y, info = ttr.round_fixed(dev, ELL, SEED, target_ranks=tgt, prec="f32")
+        times.append(time.perf_counter() - t1)
+    ttr.kernel_timing(False)
+    n, ms = ttr.kernel_timing_read("partial_contraction")
+    assert n == info["pc_launches"] * args.steps
+    b = sketch_bytes(dims, ranks, ELL, 4)
+    assert abs(b - info["pc_bytes"]) <= 1e-6 * b
+    per = info["pc_launches"]
+    return {"workload": c2_desc(), "roundings_per_s": 1.0 / pctl(times, 50),
+            "roofline": roofline(b / per, info["pc_flops"] / per, ms / 1e3 / n, FP32_MFMA_PEAK_TFLOPS,
+                                 "partial contraction, FP32 (pc_kernel<float>)",
+                                 pmc_traffic(PMC_SUMMARY, b / per)),
+            "sketch_GBps": b / (ms / 1e3 / args.steps) / 1e9, "ranks_max": max(info["ranks"])}
+
+
+def side_c3(args):
+    """The partial contractions of the adaptive C3 rounding (FP64 sketch,
+    300-row cores of 256 x 300: FP64-MFMA-bound) and that rounding's rate."""
+    import torch
+
+    import paper_2511_03598_amd as ttr
+    import ttgen
+
+    x = ttgen.c3()
+    dev = [torch.tensor(c, device="cuda") for c in x]
+    del x
+    steps = max(3, args.steps // 2)
+    for _ in range(max(1, min(args.warmup, 2))):
+        ttr.round_adaptive(dev, C3_TOL, C3_BLOCK, C3_SEED)
+    torch.cuda.synchronize()
+    ttr.kernel_timing(True, kinds=["partial_contraction"])
+    times = []
+    for _ in range(steps):
+        t1 = time.perf_counter()
+        y, info = ttr.round_adaptive(dev, C3_TOL, C3_BLOCK, C3_SEED)
+        times.append(time.perf_counter() - t1)
+    ttr.kernel_timing(False)
+    n, ms = ttr.kernel_timing_read("partial_contraction")
+    assert n == info["pc_launches"] * steps
+    per = info["pc_launches"]
+    return {"workload": "adaptive KRP TT-rounding of C3 (d=10, n=256, formal ranks 300), tol 1e-6, "
+                        "ell blocks of 16, FP64 sketch", "roundings_per_s": 1.0 / pctl(times, 50),
+            "roofline": roofline(info["pc_bytes"] / per, info["pc_flops"] / per, ms / 1e3 / n,
+                                 FP64_MFMA_PEAK_TFLOPS, "partial contraction, FP64 (pc_kernel<double>)"),
+            "sketch_GBps": info["pc_bytes"] / (ms / 1e3 / steps) / 1e9, "ranks": info["ranks"],
+            "passes": info["passes"]}
+
+
+def c4_sample(count, k):
+    """A systematic sample of k tensors of the batch (every count/k-th)."""
+    step = max(1, count // k)
+    return list(range(0, count, step))[:k]
+
+
+def c4_parity(xs, res, seeds):
+    """Sampled tensors of the last batch step against the oracle (same
+    Gaussian factors): relative difference and ranks, and their error
+    against X."""
+    from oracle import krp, tt
+    idx = c4_sample(len(xs), 6)
+    diffs, errs, same = [], [], True
+    for i in idx:
+        yg = [c.cpu().numpy() for c in res[i][0]]
+        yo, io = krp.round_adaptive(xs[i], C4_TOL, C4_BLOCK, seeds[i])
+        same = same and io["ranks"] == res[i][1]["ranks"]
+        nx = tt.norm(xs[i])
+        diffs.append(tt.diff_norm(yg, yo) / nx)
+        errs.append(tt.diff_norm(xs[i], yg) / nx)
+    return {"tensors": idx, "max_rel_diff_vs_oracle": max(diffs), "ranks_equal": same,
+            "max_rel_err_vs_X": max(errs), "tol_vs_oracle": 1e-10, "tol_vs_X": C4_TOL}
+
+
+def c4_cpu_baseline(xs, seeds, budget_s):
+    """The oracle (plain NumPy/SciPy FP64) on a systematic sample of the
+    batch: its KRP adaptive rounding (the same algorithm and Gaussian
+    factors) and its TT-SVD rounding to the same tolerance, with the BLAS
+    threads the host gives it, then single-threaded."""
+    from oracle import krp, ttsvd
+    try:
+        from threadpoolctl import threadpool_limits
+    except Exception:
+        threadpool_limits = None
+    order = c4_sample(len(xs), 64)
+
+    def rate(fn, budget):
+        fn(order[0])  # warm-up
+        n, t0 = 0, time.perf_counter()
+        for i in order:
+            fn(i)
+            n += 1
+            if time.perf_counter() - t0 >= budget:
+                break
+        el = time.perf_counter() - t0
+        return n / el, n, el
+
+    krp_fn = lambda i: krp.round_adaptive(xs[i], C4_TOL, C4_BLOCK, seeds[i])
+    svd_fn = lambda i: ttsvd.tt_svd_round(xs[i], tol=C4_TOL)
+    threads = oracle_threads()
+    v, n, el = rate(krp_fn, budget_s)
+    sv, sn, sel = rate(svd_fn, budget_s / 2)
+    out = {"value": v, "unit": "TT-roundings/s", "cores": int(threads), "kind": "oracle",
+           "sample": "the first %d of a systematic sample (every %d-th tensor) of the batch, "
+                     "KRP adaptive rounding, CPU FP64 NumPy oracle, %.1f s"
+                     % (n, max(1, len(xs) // 64), el),
+           "ttsvd_value": sv, "ttsvd_sample": "%d tensors, %.1f s" % (sn, sel)}
+    if threadpool_limits is not None:
+        with threadpool_limits(limits=1):
+            v1, n1, el1 = rate(krp_fn, budget_s / 3)
+            s1, sn1, sel1 = rate(svd_fn, budget_s / 6)
+        out.update({"one_thread_value": v1, "one_thread_sample": "%d tensors, %.1f s" % (n1, el1),
+                    "one_thread_ttsvd_value": s1,
+                    "one_thread_ttsvd_sample": "%d tensors, %.1f s" % (sn1, sel1)})
+    return out
+
+
+def run_c2(args):
+    """The fixed-rank C2 rounding with an FP32 sketch (the earlier headline
+    workload), with the per-kind kernel breakdown and the served-concurrency
+    figure."""
+    import torch
 
     import paper_2511_03598_amd as ttr
     import ttgen
@@ -157,11 +433,6 @@ def main():
     for _ in range(args.warmup):
         y, info = step()
     torch.cuda.synchronize()
-    # Timed region: K whole roundings, with the library's HIP-event timers on
-    # around each partial-contraction launch only (the roofline's launch
-    # duration); the breakdown over all kernel kinds comes from a separate
-    # untimed pass, since event pairs around every GEMM, QR and SVD add about
-    # a tenth to the rounding time.
     ttr.kernel_timing(True, kinds=["partial_contraction"])
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
@@ -177,27 +448,19 @@ def main():
     ms_per_step = gpu_ms / args.steps
     value = args.steps / (gpu_ms / 1e3)
     kt = {k: ttr.kernel_timing_read(k) for k in ttr.KERNEL_KINDS}
-    # per-kind breakdown (untimed pass with every kind's timers on)
     ttr.kernel_timing(True)
     for _ in range(args.steps):
         step()
     torch.cuda.synchronize()
     ttr.kernel_timing(False)
     kbreak = {k: ttr.kernel_timing_read(k)[1] / args.steps for k in ttr.KERNEL_KINDS}
-
-    # Roofline of the partial-contraction kernel: algorithmic bytes of one
-    # pass / launches per pass, over the average recorded launch duration.
     npc_launches, pc_ms = kt["partial_contraction"]
-    npc = D - 1
+    npc = info["pc_launches"]
     assert npc_launches == npc * args.steps, (npc_launches, npc, args.steps)
     pc_bytes = sketch_bytes(dims, ranks, ELL, 4)
     avg_launch_s = pc_ms / 1e3 / npc_launches
-    achieved = pc_bytes / npc / avg_launch_s / 1e9
-    sketch_gbps = pc_bytes / (pc_ms / 1e3 / args.steps) / 1e9
-    traffic = pmc_traffic(pc_bytes / npc)
-
     out = {
-        "metric": "TT-roundings/s + sketch GB/s vs plain & TT-SVD at rel err <=1e-6",
+        "metric": "TT-roundings/s (fixed-rank C2, FP32 sketch)",
         "value": value,
         "unit": "TT-roundings/s",
         "n_gpus": 1,
@@ -209,27 +472,20 @@ def main():
         "vs_baseline": None,
         "dtype": "f32 sketch / f64 sweep",
         "data": "synthetic",
-        "config": {"workload": workload_desc(), "d": D, "n": N, "formal_rank": R * TERMS,
+        "config": {"workload": c2_desc(), "d": D, "n": N, "formal_rank": R * TERMS,
                    "ell": ELL, "target_rank": TARGET, "seed": SEED},
-        "sketch_GBps": sketch_gbps,
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic,
-                     "kernel": "partial contraction (pc_kernel<float>)",
-                     "bytes_per_launch": pc_bytes / npc, "avg_launch_us": avg_launch_s * 1e6},
+        "sketch_GBps": pc_bytes / (pc_ms / 1e3 / args.steps) / 1e9,
+        "roofline": roofline(pc_bytes / npc, info["pc_flops"] / npc, avg_launch_s,
+                             FP32_MFMA_PEAK_TFLOPS, "partial contraction (pc_kernel<float>)",
+                             pmc_traffic(PMC_SUMMARY, pc_bytes / npc)),
         "kernel_ms_per_step": kbreak,
         "wall_s": wall,
     }
-    # Headroom beyond one stream: a single rounding is latency-bound (its
-    # SVDs and QR factorisations each run on one CU), so the same rounding
-    # is also submitted 32 times to the library's server (8 workers, one HIP
-    # stream each).  Reported beside `value`, which stays the one-stream rate.
-    if args.no_concurrent:
-        srv = None
-    else:
+    if not args.no_concurrent:
         srv = ttr.Server(workers=8)
-    def submit():
-        return srv.submit(dev, kind="fixed", ell=ELL, target_ranks=tgt, seed=SEED, prec="f32")
-    if srv is not None:
+
+        def submit():
+            return srv.submit(dev, kind="fixed", ell=ELL, target_ranks=tgt, seed=SEED, prec="f32")
         for t in [submit() for _ in range(8)]:
             srv.wait(t)
         nreq = 32
@@ -249,56 +505,6 @@ def main():
         nx = tt.norm(x)
         out["parity"] = {"rel_diff_vs_oracle": tt.diff_norm(yh, yo) / nx,
                          "ranks_equal": info["ranks"] == io["ranks"], "tol": 1e-5}
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(x, args.cpu_budget)
-    print(json.dumps(out), flush=True)
-
-
-def run_c4(args):
-    """Batched adaptive rounding (tol 1e-6, ell blocks of 16) of `count`
-    independent TTs of uneven d, n and ranks, against the plain loop of
-    single calls on one stream.  Both produce bitwise the same results."""
-    import torch
-
-    import paper_2511_03598_amd as ttr
-    import ttgen
-    from oracle import tt
-
-    t0 = time.perf_counter()
-    xs = ttgen.c4(count=args.count)
-    gen_s = time.perf_counter() - t0
-    devs = [[torch.tensor(c, device="cuda") for c in x] for x in xs]
-    seeds = [42 + t for t in range(len(xs))]
-    tol, blk = 1e-6, 16
-    nbytes = sum(c.numel() * 8 for x in devs for c in x)
-    # warm-up (workspaces, code objects)
-    ttr.round_adaptive_batch(devs[:8], tol, blk, seeds[:8])
-    for i in range(4):
-        ttr.round_adaptive(devs[i], tol, blk, seeds[i])
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    plain = [ttr.round_adaptive(devs[i], tol, blk, seeds[i]) for i in range(len(devs))]
-    torch.cuda.synchronize()
-    t_plain = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    batch = ttr.round_adaptive_batch(devs, tol, blk, seeds)
-    torch.cuda.synchronize()
-    t_batch = time.perf_counter() - t0
-    same = all(p[1]["ranks"] == b[1]["ranks"] and all(torch.equal(u, v) for u, v in zip(p[0], b[0]))
-               for p, b in zip(plain, batch))
-    sample = list(range(0, len(xs), max(1, len(xs) // 6)))[:6]
-    errs = [tt.rel_err(xs[i], [c.cpu().numpy() for c in batch[i][0]]) for i in sample]
-    out = {
-        "metric": "TT-roundings/s (batched, C4)", "value": len(xs) / t_batch,
-        "unit": "TT-roundings/s", "n_gpus": 1, "higher_is_better": True, "data": "synthetic",
-        "config": {"workload": "C4: %d TTs, d in [4,16], n in [16,128], formal ranks in [8,128], "
-                               "sum of 3 N(0,1) TTs weighted (1, 1e-4, 1e-8), adaptive tol 1e-6, "
-                               "ell blocks of 16, FP64" % len(xs),
-                   "workers": 8, "input_GB": nbytes / 1e9},
-        "plain_loop_value": len(xs) / t_plain, "speedup_vs_plain": t_plain / t_batch,
-        "batch_s": t_batch, "plain_s": t_plain, "bitwise_equal_to_plain": same,
-        "rel_err_sample": {"tensors": sample, "max": max(errs)}, "generate_s": gen_s,
-    }
     print(json.dumps(out), flush=True)
 
 

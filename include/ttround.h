@@ -103,6 +103,12 @@ typedef struct {        /* diagnostics of the calling thread's last rounding */
     int32_t qr_retries; /* 1 if the rounding was repeated because a CholeskyQR
                            broke down while the Householder fallback was
                            deferred (the result is that of the repeat)       */
+    int64_t pc_launches; /* partial-contraction launches (one per core and
+                            pass, Sec. 3.1)                                  */
+    double pc_bytes;    /* their algorithmic bytes: one float64 read of every
+                           contracted core plus the W_k writes               */
+    double pc_flops;    /* their flops by the Sec. 3.1 cost model:
+                           2 r_{k-1} n_k r_k l + 2 r_{k-1} r_k l per core      */
 } tt_info;
 
 /* Output capacity (elements) per core: cap[k-1] = c_{k-1} n_k c_k with

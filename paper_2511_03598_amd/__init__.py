@@ -52,7 +52,9 @@ class _Opts(ctypes.Structure):
 class _Info(ctypes.Structure):
     _fields_ = [("tau", ctypes.c_double), ("nrmx", ctypes.c_double),
                 ("min_margin", ctypes.c_double), ("passes", ctypes.c_int32),
-                ("iterations", ctypes.c_int32), ("qr_retries", ctypes.c_int32)]
+                ("iterations", ctypes.c_int32), ("qr_retries", ctypes.c_int32),
+                ("pc_launches", ctypes.c_int64), ("pc_bytes", ctypes.c_double),
+                ("pc_flops", ctypes.c_double)]
 
 
 class _ServerCfg(ctypes.Structure):
@@ -281,7 +283,8 @@ def last_info():
     i = _Info()
     _check(lib().tt_last_info(ctypes.byref(i)))
     return {"tau": i.tau, "nrmx": i.nrmx, "min_margin": i.min_margin, "passes": i.passes,
-            "iterations": i.iterations, "qr_retries": i.qr_retries}
+            "iterations": i.iterations, "qr_retries": i.qr_retries,
+            "pc_launches": i.pc_launches, "pc_bytes": i.pc_bytes, "pc_flops": i.pc_flops}
 
 
 def gaussian_factor(seed, mode, n, col0, ncols, device="cuda", stream=None):

@@ -84,6 +84,9 @@ void store_info(const ttr::RoundInfo& i) {
     g_info.passes = i.passes;
     g_info.iterations = i.iterations;
     g_info.qr_retries = i.qr_retries;
+    g_info.pc_launches = i.pc_launches;
+    g_info.pc_bytes = i.pc_bytes;
+    g_info.pc_flops = i.pc_flops;
 }
 
 
@@ -94,6 +97,9 @@ void fill_info(tt_info& o, const ttr::RoundInfo& i) {
     o.passes = i.passes;
     o.iterations = i.iterations;
     o.qr_retries = i.qr_retries;
+    o.pc_launches = i.pc_launches;
+    o.pc_bytes = i.pc_bytes;
+    o.pc_flops = i.pc_flops;
 }
 
 int64_t out_capacity_total(const ttr::Shape& s, std::vector<int64_t>* per_core) {

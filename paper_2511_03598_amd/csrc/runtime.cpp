@@ -294,6 +294,12 @@ struct Sketch {
     int64_t ncols = 0;  // generated columns (storage col == global col - gcol0)
     int64_t gcol0 = 0;
     int passes = 0;
+    // Algorithmic work of the partial contractions so far (Sec. 3.1 cost
+    // model): one float64 read of each contracted core and one write of
+    // each W_k column block per pass, 2 r_{k-1} n_k r_k l + 2 r_{k-1} r_k l
+    // flops per core (2 r_{d-1} n_d l for the last), one launch per core.
+    int64_t pc_launches = 0;
+    double pc_bytes = 0.0, pc_flops = 0.0;
 
     Sketch(const Summands& xs, uint64_t sd, int pr, int64_t cap, hipStream_t stream, Workspace& w_,
            int64_t global_col0 = 0)
@@ -413,6 +419,16 @@ struct Sketch {
                     else
                         launch_pc_f32(a, st);
                 }
+            }
+        }
+        const double esz = prec == 0 ? 8.0 : (prec == 1 ? 4.0 : 2.0);
+        for (int i = 0; i < x.m(); ++i) {
+            const Shape& si = x.sh[i];
+            for (int k = d; k >= t; --k) {
+                const double r0 = (double)si.r[k - 1], nk = (double)si.n[k - 1], r1 = (double)si.r[k];
+                pc_bytes += 8.0 * r0 * nk * r1 + esz * r0 * (double)nc;
+                pc_flops += 2.0 * r0 * nk * r1 * (double)nc + (k < d ? 2.0 * r0 * r1 * (double)nc : 0.0);
+                ++pc_launches;
             }
         }
         ncols += nc;
@@ -774,6 +790,9 @@ static bool round_fixed_once(Workspace& ws, const Summands& x, const int64_t* ta
     final_sync(ws, st);
     info = RoundInfo{};
     info.passes = sk.passes;
+    info.pc_launches = sk.pc_launches;
+    info.pc_bytes = sk.pc_bytes;
+    info.pc_flops = sk.pc_flops;
     return !qr_broke(ws);
 }
 
@@ -919,6 +938,9 @@ static bool round_adaptive_once(Workspace& ws, const Summands& x, double tol, in
     }
     final_sync(ws, st);
     info.passes = sk.passes;
+    info.pc_launches = sk.pc_launches;
+    info.pc_bytes = sk.pc_bytes;
+    info.pc_flops = sk.pc_flops;
     if (info.iterations == 0) info.min_margin = INFINITY;
     return !qr_broke(ws);
 }

@@ -26,6 +26,8 @@ struct RoundInfo {
     double tau = 0, nrmx = 0, min_margin = 0;
     int passes = 0, iterations = 0;
     int qr_retries = 0;  // 1: repeated with the eager Householder fallback
+    int64_t pc_launches = 0;              // partial-contraction launches
+    double pc_bytes = 0.0, pc_flops = 0.0;  // their algorithmic bytes and flops
 };
 
 // Output cores: caller-owned device buffers with capacities (elements).

@@ -121,10 +121,16 @@ def test_fixed_truncation_without_spectral_gap(lib, seed):
     _check_orth(yg, ig)
 
 
-def _ranks_equal_or_tie(ig, io, rg, ro):
+def _ranks_equal_or_tie(ig, io, rg, ro, x=None, results=(), tol=None):
+    """Equal ranks, or a decision within 1e-6 of tau (a tie), in which case
+    every result in `results` must meet the adaptive bound ||X - Y|| <=
+    tol ||X|| (with the 1.5 allowance for the randomized estimate)."""
     if rg == ro:
         return True
-    return min(ig["min_margin"], io["min_margin"]) < 1e-6
+    if not min(ig["min_margin"], io["min_margin"]) < 1e-6:
+        return False
+    nx = tt.norm(x)
+    return all(tt.diff_norm(x, y) <= 1.5 * tol * nx for y in results)
 
 
 @pytest.mark.parametrize("recompress", [0, 1])
@@ -135,7 +141,7 @@ def test_adaptive_c1(lib, recompress):
     yg = to_host(yg)
     yo, io = krp.round_adaptive(x, 1e-8, 4, 42, recompress=recompress)
     assert abs(ig["nrmx"] - io["nrmx"]) <= 1e-12 * io["nrmx"]
-    assert _ranks_equal_or_tie(ig, io, ig["ranks"], io["ranks"])
+    assert ig["ranks"] == io["ranks"]
     assert rel_tensor_diff(x, yg, yo) <= TOL["f64"]
     assert tt.rel_err(x, yg) <= 1e-8
     if recompress:
@@ -154,7 +160,7 @@ def test_adaptive_given_norm_and_regeneration(lib):
         yg = to_host(yg)
         yo, io = krp.round_adaptive(x, 1e-5, 2, seed, nrmx=nrm)
         assert ig["passes"] >= 2
-        assert _ranks_equal_or_tie(ig, io, ig["ranks"], io["ranks"])
+        assert _ranks_equal_or_tie(ig, io, ig["ranks"], io["ranks"], x, (yg, yo), 1e-5)
         if ig["ranks"] == io["ranks"]:
             assert rel_tensor_diff(x, yg, yo) <= TOL["f64"]
         _check_orth(yg, ig)
@@ -164,8 +170,10 @@ def test_adaptive_d2_edge(lib):
     x = ttgen.small_random(31, 2, [9, 40], [9])
     yg, ig = lib.round_adaptive(to_dev(x), 1e-3, 3, 1)
     yo, io = krp.round_adaptive(x, 1e-3, 3, 1)
-    assert _ranks_equal_or_tie(ig, io, ig["ranks"], io["ranks"])
-    assert rel_tensor_diff(x, to_host(yg), yo) <= TOL["f64"]
+    yg = to_host(yg)
+    assert _ranks_equal_or_tie(ig, io, ig["ranks"], io["ranks"], x, (yg, yo), 1e-3)
+    if ig["ranks"] == io["ranks"]:
+        assert rel_tensor_diff(x, yg, yo) <= TOL["f64"]
 
 
 def test_deterministic_bitwise(lib):

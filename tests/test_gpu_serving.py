@@ -130,3 +130,38 @@ def test_server_poll_until_done(lib):
             srv.poll(t)
     finally:
         srv.close()
+
+
+def test_server_failed_request_leaves_neighbours_intact(lib):
+    """A request that the library rejects after its sweep has been queued
+    (Remark 2 recompression of ranks above the truncation kernel's limit)
+    returns TT_EUNSUPPORTED, and the requests served beside it stay bitwise
+    equal to their solo runs (the failed request's buffers go back to the
+    pools only after its stream has drained)."""
+    wide = ttgen.c3(seed=7, d=4, n=16, r=100, noise_r=10, decay=40.0)
+    dw = to_dev(wide)
+    y_alone, i_alone = lib.round_adaptive(dw, 1e-6, 16, 3)
+    assert max(i_alone["ranks"]) > 64
+    xs = _mix(6, 600)
+    devs = [to_dev(x) for x in xs]
+    solo = [lib.round_adaptive(dv, 1e-6, 4, 20 + i) for i, dv in enumerate(devs)]
+    srv = lib.Server(workers=4)
+    try:
+        tickets = []
+        for i, dv in enumerate(devs):
+            tickets.append((i, srv.submit(dv, tol=1e-6, ell_block=4, seed=20 + i)))
+            if i % 2 == 0:
+                tickets.append((-1, srv.submit(dw, tol=1e-6, ell_block=16, seed=3, recompress=1)))
+        for i, t in tickets:
+            if i < 0:
+                with pytest.raises(lib.TTError, match="EUNSUPPORTED"):
+                    srv.wait(t)
+            else:
+                ys, info = srv.wait(t)
+                assert info["ranks"] == solo[i][1]["ranks"]
+                assert _same(to_host(ys), to_host(solo[i][0])), i
+    finally:
+        srv.close()
+    # the failure left no error behind for later calls on this thread
+    y2, i2 = lib.round_adaptive(dw, 1e-6, 16, 3)
+    assert _same(to_host(y2), to_host(y_alone))
