@@ -128,6 +128,25 @@ tt_status tt_out_capacity(const tt_view* x, const int64_t* target_ranks, int64_t
 tt_status tt_round_fixed(const tt_view* x, const int64_t* target_ranks, int64_t ell,
                          uint64_t seed, const tt_opts* opts, tt_out* y);
 
+/* Allocation-free variant of tt_round_fixed, for callers that cannot
+ * allocate device memory (code under stream capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same arguments, result (bitwise the
+ * same outputs and ranks) and errors as tt_round_fixed, but every device
+ * buffer the rounding needs besides its inputs and outputs is carved from a
+ * static device array of TT_NOALLOC_SCRATCH_BYTES that the library holds on
+ * each GPU it runs on until the process ends; no hipMalloc, hipFree or
+ * pinned host allocation happens in the call, and kernel timing
+ * (tt_kernel_timing) does not record it.  TT_ENOMEM when the shape's
+ * workspace estimate (tt_workspace_bytes with ell_max = ell) exceeds the
+ * array, checked before any work is queued.  All calls on one GPU share the
+ * array: the library serialises the calls of this process per device (each
+ * returns after its stream is synchronized), and work queued on the array
+ * by overlapping calls from elsewhere would race.  The Householder fallback
+ * of the QRs is launched eagerly, so tt_last_info().qr_retries is 0. */
+#define TT_NOALLOC_SCRATCH_BYTES (64u << 20)
+tt_status tt_round_fixed_noalloc(const tt_view* x, const int64_t* target_ranks, int64_t ell,
+                                 uint64_t seed, const tt_opts* opts, tt_out* y);
+
 /* Adaptive-rank rounding to relative tolerance tol > 0 (Sec. 3.3, Algorithm
  * "Adaptive Rank TT-Rounding: Randomize-then-Orthogonalize using KRP", with
  * the residual sketching of Sec. 3.3 and Remark 1).  With tau =

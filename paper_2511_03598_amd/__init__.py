@@ -12,7 +12,7 @@ r_0 = r_d = 1 (contiguous).
 import ctypes
 import os
 
-__all__ = ["lib", "round_fixed", "round_adaptive", "gaussian_factor", "philox4x32_10",
+__all__ = ["lib", "round_fixed", "round_fixed_noalloc", "round_adaptive", "gaussian_factor", "philox4x32_10",
            "partial_contractions", "qr", "svd_small", "out_capacity", "last_info", "TTError",
            "PREC_F64", "PREC_F32", "PREC_BF16", "LIB_PATH"]
 
@@ -91,6 +91,7 @@ def lib():
         sig = {
             "tt_out_capacity": [P(_View), P(i64), P(i64)],
             "tt_round_fixed": [P(_View), P(i64), i64, u64, P(_Opts), P(_Out)],
+            "tt_round_fixed_noalloc": [P(_View), P(i64), i64, u64, P(_Opts), P(_Out)],
             "tt_round_adaptive": [P(_View), dbl, i64, u64, P(_Opts), P(_Out)],
             "tt_last_info": [P(_Info)],
             "tt_gaussian_factor": [u64, i32, i64, i64, i64, vp, vp],
@@ -203,6 +204,22 @@ def round_fixed(cores, ell, seed, target_ranks=None, prec="f64", stream=None):
         tg = (ctypes.c_int64 * (d + 1))(*[int(x) for x in target_ranks])
     o = _opts(prec, 0.0, 0.0, 0, stream)
     return _run(cores, lambda h, out: lib().tt_round_fixed(
+        ctypes.byref(h.view), tg, int(ell), ctypes.c_uint64(seed), ctypes.byref(o),
+        ctypes.byref(out)))
+
+
+def round_fixed_noalloc(cores, ell, seed, target_ranks=None, prec="f64", stream=None):
+    """round_fixed through the allocation-free entry point (the library's
+    static scratch array instead of its workspace pool).  The output
+    buffers are still allocated here by torch.  Returns (cores, info)."""
+    d = len(cores)
+    tg = None
+    if target_ranks is not None:
+        if len(target_ranks) != d + 1:
+            raise ValueError("target_ranks needs d+1 entries")
+        tg = (ctypes.c_int64 * (d + 1))(*[int(x) for x in target_ranks])
+    o = _opts(prec, 0.0, 0.0, 0, stream)
+    return _run(cores, lambda h, out: lib().tt_round_fixed_noalloc(
         ctypes.byref(h.view), tg, int(ell), ctypes.c_uint64(seed), ctypes.byref(o),
         ctypes.byref(out)))
 

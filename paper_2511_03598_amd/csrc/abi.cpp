@@ -192,6 +192,26 @@ tt_status tt_round_fixed(const tt_view* x, const int64_t* target_ranks, int64_t 
     });
 }
 
+tt_status tt_round_fixed_noalloc(const tt_view* x, const int64_t* target_ranks, int64_t ell,
+                                 uint64_t seed, const tt_opts* opts, tt_out* y) {
+    return guarded([&] {
+        ttr::Shape s = view_shape(x);
+        ttr::Options o = make_opts(opts);
+        if (ell < 1) throw ttr::Error(TT_EINVAL, "ell must be >= 1");
+        if (target_ranks) {
+            if (target_ranks[0] != 1 || target_ranks[s.d] != 1)
+                throw ttr::Error(TT_EINVAL, "target_ranks[0] and [d] must be 1");
+            for (int k = 1; k < s.d; ++k)
+                if (target_ranks[k] < 1) throw ttr::Error(TT_EINVAL, "target ranks must be >= 1");
+        }
+        ttr::OutCores oc = out_of(y, s.d);
+        ttr::RoundInfo info;
+        ttr::round_fixed_noalloc(s, x->cores, target_ranks, ell, seed, o, oc, info);
+        y->orth = oc.orth;
+        store_info(info);
+    });
+}
+
 namespace {
 ttr::Summands sum_of(const tt_view* xs, int32_t count, const double* weights) {
     if (!xs) throw ttr::Error(TT_EINVAL, "null tt_view array");

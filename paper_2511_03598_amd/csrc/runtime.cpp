@@ -29,11 +29,36 @@ namespace ttr {
 // ---------------------------------------------------------------------------
 namespace {
 
+// A fixed region of device memory handed out front to back: the scratch of
+// the allocation-free entry point.  A carve that does not fit throws
+// ENOMEM; nothing is ever returned before the region is reset.
+struct Arena {
+    char* base = nullptr;
+    size_t size = 0, used = 0;
+    void* carve(size_t bytes) {
+        const size_t b = (bytes + 255) / 256 * 256;
+        if (b > size - used)
+            throw Error(-2, "allocation-free scratch exhausted: " + std::to_string(used + b) +
+                                " bytes needed, " + std::to_string(size) + " available");
+        void* p = base + used;
+        used += b;
+        return p;
+    }
+};
+
 struct DevBuf {
     void* p = nullptr;
     size_t cap = 0;
+    Arena* arena = nullptr;  // set: carve from the arena instead of hipMalloc
     void* get(size_t bytes) {
         if (bytes == 0) bytes = 256;
+        if (bytes > cap && arena) {
+            // a larger request takes a new slice (contents are never kept
+            // across a growth, as with hipMalloc below)
+            p = arena->carve(bytes);
+            cap = (bytes + 255) / 256 * 256;
+            return p;
+        }
         if (bytes > cap) {
             if (p) TTR_HIP(hipFree(p));
             p = nullptr;
@@ -53,7 +78,7 @@ struct DevBuf {
         return static_cast<T*>(get(count * sizeof(T)));
     }
     ~DevBuf() {
-        if (p) (void)hipFree(p);
+        if (p && !arena) (void)hipFree(p);
     }
 };
 
@@ -70,14 +95,30 @@ struct Workspace {
     double* host = nullptr;  // pinned scalars
     int* host_int = nullptr;
     int zeroed_qrcnt = 0, zeroed_sumcnt = 0;
+    double host_plain[64];  // host scalars of an arena workspace (not pinned)
+    bool pinned = false;
     Workspace() {
         TTR_HIP(hipGetDevice(&device));
         TTR_HIP(hipHostMalloc((void**)&host, 64 * sizeof(double), hipHostMallocDefault));
+        pinned = true;
         host_int = reinterpret_cast<int*>(host + 32);
     }
-    ~Workspace() {
-        if (host) (void)hipHostFree(host);
+    // Every device buffer carved from `a`, host scalars in plain memory:
+    // constructing and using this workspace allocates nothing.
+    explicit Workspace(Arena* a) {
+        TTR_HIP(hipGetDevice(&device));
+        host = host_plain;
+        host_int = reinterpret_cast<int*>(host + 32);
+        for (DevBuf* b : {&omega, &w, &colexp, &maxexp, &dn, &doff, &y0, &y1, &q, &sbuf, &tbuf, &m, &qrws,
+                          &cqws, &qrcnt, &part, &scal, &sumpart, &sumcnt, &small1, &small2, &small3,
+                          &small4, &tint, &tmp, &qrsticky})
+            b->arena = a;
     }
+    ~Workspace() {
+        if (host && pinned) (void)hipHostFree(host);
+    }
+    Workspace(const Workspace&) = delete;
+    Workspace& operator=(const Workspace&) = delete;
     int* qr_counters(int n, hipStream_t s) {
         const size_t before = qrcnt.cap;
         int* p = qrcnt.as<int>(std::max(n, 1024));
@@ -819,6 +860,31 @@ void round_fixed(const Shape& s, const double* const* cores, const int64_t* targ
     round_fixed(single_term(s, cores), target, ell, seed, o, y, info);
 }
 
+// The fixed-rank rounding with every device buffer carved from the
+// caller's region (the allocation-free entry point).  The Householder
+// fallback is launched eagerly (a breakdown costs no repeat and no host
+// readback); the result is the same as round_fixed's.  On an error the
+// stream is drained before returning, so the region is idle again.
+void round_fixed_in(void* region, size_t region_bytes, const Shape& s, const double* const* cores,
+                    const int64_t* target, int64_t ell, uint64_t seed, const Options& o, OutCores& y,
+                    RoundInfo& info) {
+    if (ell < 1) throw Error(-1, "ell must be >= 1");
+    if (ell > 64) throw Error(-6, "fixed-rank sketch size ell > 64 is not supported");
+    Arena arena;
+    arena.base = static_cast<char*>(region);
+    arena.size = region_bytes;
+    Workspace ws(&arena);
+    TimingPause no_timing;
+    try {
+        round_fixed_once(ws, single_term(s, cores), target, ell, seed, o, y, info);
+    } catch (...) {
+        (void)hipStreamSynchronize(o.stream);
+        (void)hipGetLastError();
+        throw;
+    }
+    info.qr_retries = 0;
+}
+
 // ---------------------------------------------------------------------------
 // Adaptive rank (Sec. 3.3)
 // ---------------------------------------------------------------------------
@@ -1099,8 +1165,18 @@ void timing_read(int kind, int64_t* launches, double* total_ms) {
     *total_ms = t.ms[kind];
 }
 
+namespace {
+// Set while an allocation-free rounding runs on this thread: its launches
+// are not timed (recording them would create events).
+thread_local bool t_timing_off = false;
+}  // namespace
+
+TimingPause::TimingPause() : prev_(t_timing_off) { t_timing_off = true; }
+TimingPause::~TimingPause() { t_timing_off = prev_; }
+
 TimedScope::TimedScope(int kind, hipStream_t s, int launches)
     : kind_(kind), s_(s), launches_(launches) {
+    if (t_timing_off) return;
     TimingState& t = timing();
     std::lock_guard<std::mutex> lk(t.mu);
     if (!((t.kinds >> kind) & 1u)) return;

@@ -74,6 +74,16 @@ void round_fixed(const Shape& s, const double* const* cores, const int64_t* targ
 void round_adaptive(const Shape& s, const double* const* cores, double tol, int64_t ell_block,
                     uint64_t seed, const Options& o, OutCores& y, RoundInfo& info);
 
+// round_fixed with all device memory carved from `region` (region_bytes):
+// allocates nothing; the caller serialises calls that share a region.
+void round_fixed_in(void* region, size_t region_bytes, const Shape& s, const double* const* cores,
+                    const int64_t* target, int64_t ell, uint64_t seed, const Options& o, OutCores& y,
+                    RoundInfo& info);
+
+// round_fixed_in on this device's allocation-free scratch array (noalloc.hip).
+void round_fixed_noalloc(const Shape& s, const double* const* cores, const int64_t* target,
+                         int64_t ell, uint64_t seed, const Options& o, OutCores& y, RoundInfo& info);
+
 void gaussian_factor(uint64_t seed, int mode, int64_t n, int64_t col0, int64_t ncols, double* out,
                      hipStream_t st);
 void partial_contractions(const Shape& s, const double* const* cores, uint64_t seed, int64_t col0,
@@ -87,6 +97,18 @@ int64_t svd_small(const double* a, int64_t p, int64_t q, double* g, double* v, d
 enum { KT_PC = 0, KT_GEMM = 1, KT_QR = 2, KT_SVD = 3, KT_KINDS = 4 };
 void timing_enable(unsigned kinds);  // bit k records kind k; 0 stops
 void timing_read(int kind, int64_t* launches, double* total_ms);
+
+// RAII: no TimedScope on this thread records anything while it lives.
+class TimingPause {
+   public:
+    TimingPause();
+    ~TimingPause();
+    TimingPause(const TimingPause&) = delete;
+    TimingPause& operator=(const TimingPause&) = delete;
+
+   private:
+    bool prev_;
+};
 
 // RAII scope: records a start event on construction and a stop event on
 // destruction when timing is enabled; no-op otherwise.  `launches` is the

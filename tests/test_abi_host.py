@@ -165,3 +165,21 @@ def test_sum_capacity_and_validation_host_only():
     assert L.tt_round_sum_fixed(views, 2, None, None, 0, 1, None, ctypes.byref(outs)) == -1
     assert L.tt_round_sum_adaptive(views, 2, None, 0.0, 4, 1, None, ctypes.byref(outs)) == -1
     assert L.tt_round_sum_adaptive(views_bad, 2, None, 1e-6, 4, 1, None, ctypes.byref(outs)) == -1
+
+
+def test_noalloc_entry_point_rejects_oversize_on_the_host():
+    """tt_round_fixed_noalloc refuses a shape whose workspace estimate
+    exceeds TT_NOALLOC_SCRATCH_BYTES before any device call."""
+    import paper_2511_03598_amd as ttr
+    L = ttr.lib()
+    text = open(HEADER).read()
+    m = re.search(r"#define TT_NOALLOC_SCRATCH_BYTES \((\d+)u << (\d+)\)", text)
+    assert m and int(m.group(1)) << int(m.group(2)) == 64 << 20
+    v, keep = _view(3, [4096, 4096, 64], [1, 300, 300, 1], [1, 2, 3])
+    ranks = (ctypes.c_int64 * 4)()
+    ptrs = (ctypes.c_void_p * 3)(1, 2, 3)
+    cap = (ctypes.c_int64 * 3)(1 << 40, 1 << 40, 1 << 40)
+    out = ttr._Out(3, ranks, ptrs, cap, 0)
+    st = L.tt_round_fixed_noalloc(ctypes.byref(v), None, 60, ctypes.c_uint64(1), None, ctypes.byref(out))
+    assert st == -2
+    assert b"scratch" in L.tt_last_error()
