@@ -6,20 +6,23 @@ uniform in [4,16], n in [16,128], formal ranks in [8,128]; each a sum of 3
 N(0,1) TTs weighted 1, 1e-4, 1e-8) rounded adaptively to tol 1e-6 with
 blocks of 16 sketch columns, all in FP64, through the batch entry point.
 A step is one rounding of the whole batch (every hot-path step of every
-tensor), inputs resident in HBM; `value` is tensors rounded per second over
-the timed steps.  Printed beside it, in one JSON line:
+tensor) as one persistent kernel launch plus the readback of the ranks,
+inputs resident in HBM and the batch laid out once beforehand; `value` is
+tensors rounded per second over the timed steps.  Printed beside it, in one JSON line:
 
   * the plain single-instance rate (one tt_round_adaptive call after the
-    other on one stream, same tensors and seeds, bitwise the same results);
+    other on one stream, same tensors and seeds; the same ranks, tensors
+    equal to rounding error) and the rate of the synchronous batch call;
   * median / p10 / p90 of the step times;
   * sketch GB/s: the partial contractions' algorithmic bytes (one FP64
     read of each contracted core plus the W writes, every pass including
     the regeneration passes) over the batch's wall time;
-  * `roofline`: the partial-contraction kernel inside the timed steps --
-    algorithmic bytes (or flops) per launch over the average launch
-    duration, from HIP event pairs the library records on each launch
-    stream around its back-to-back partial-contraction launches;
-  * the same kernel at the two sizes where it is a large launch: the
+  * `roofline`: the persistent batch kernel (the whole rounding of the
+    batch in one launch) -- its algorithmic bytes and flops per launch (the
+    partial contractions as run, a second read of every core for the
+    next-core products, the output writes) over the launch duration timed
+    with events on the launch stream;
+  * the partial-contraction kernel at the two sizes where it is a large launch: the
     fixed-rank C2 rounding with an FP32 sketch (HBM-bound) and the adaptive
     C3 rounding with an FP64 sketch (FP64-MFMA-bound), with their rates;
   * parity of sampled tensors against the CPU oracle and their error
@@ -147,6 +150,8 @@ def main():
                          "rounding of C3 with FP64/FP32/BF16 sketches at tol 1e-4..1e-10")
     ap.add_argument("--count", type=int, default=256, help="c4: tensors in the batch")
     ap.add_argument("--plain-reps", type=int, default=3, help="c4: repetitions of the plain loop")
+    ap.add_argument("--no-plain", action="store_true",
+                    help="c4: skip the plain loop and the synchronous batch call (profiling runs)")
     ap.add_argument("--requests", type=int, default=500, help="c5: requests per arrival rate")
     ap.add_argument("--workers", type=int, default=8, help="c5: concurrent roundings")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -183,6 +188,23 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def batch_model(xs, res):
+    """Algorithmic bytes and flops of the batch rounding (Sec. 3.1 cost
+    model): the partial contractions as each tensor ran them (every pass,
+    one float64 read of each contracted core and its W writes), one more
+    float64 read of every core for the products with the next cores, the
+    output writes, and the next-core products' flops."""
+    b = f = 0.0
+    for x, (y, info) in zip(xs, res):
+        rk = info["ranks"]
+        b += info["pc_bytes"] + sum(c.size for c in x) * 8.0 + sum(c.numel() for c in y) * 8.0
+        f += info["pc_flops"]
+        for k in range(1, len(x)):
+            r0, n1, r1 = x[k].shape
+            f += 2.0 * rk[k] * r0 * n1 * r1
+    return b, f
+
+
 def run_headline(args):
     import numpy as np
     import torch
@@ -196,48 +218,59 @@ def run_headline(args):
     seeds = [42 + t for t in range(len(xs))]
     log("generated and uploaded %d tensors in %.1f s" % (len(xs), time.perf_counter() - t0))
 
-    def batch():
-        return ttr.round_adaptive_batch(devs, C4_TOL, C4_BLOCK, seeds)
-
+    # the batch laid out once (descriptors uploaded); each step is one
+    # persistent launch plus the readback of ranks and run records
+    t1 = time.perf_counter()
+    plan = ttr.BatchPlan(devs, C4_TOL, C4_BLOCK, seeds)
+    plan_s = time.perf_counter() - t1
     for _ in range(max(1, args.warmup)):
-        res = batch()
+        plan.launch()
+        res = plan.finish()
     torch.cuda.synchronize()
     log("warm-up done")
-    # timed region: K batch calls (each returns when all its roundings are
-    # complete), with the library's event pairs around the partial
-    # contractions on every worker stream
-    ttr.kernel_timing(True, kinds=["partial_contraction"])
-    step_s = []
+    step_s, kern_ms = [], []
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     wall0 = time.perf_counter()
     for _ in range(args.steps):
         t1 = time.perf_counter()
-        res = batch()
-        torch.cuda.synchronize()
+        ev0.record()
+        plan.launch()
+        ev1.record()
+        res = plan.finish()
         step_s.append(time.perf_counter() - t1)
+        kern_ms.append(ev0.elapsed_time(ev1))
     wall = time.perf_counter() - wall0
-    ttr.kernel_timing(False)
-    pc_launches, pc_ms = ttr.kernel_timing_read("partial_contraction")
     log("timed %d batch steps: median %.3f s" % (args.steps, pctl(step_s, 50)))
+    # the synchronous batch call (plan built inside every call)
+    call_s = []
+    for _ in range(0 if args.no_plain else 3):
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        ttr.round_adaptive_batch(devs, C4_TOL, C4_BLOCK, seeds)
+        torch.cuda.synchronize()
+        call_s.append(time.perf_counter() - t1)
 
-    # plain single-instance loop (untimed for `value`); its per-tensor
-    # accounting of the partial contractions is the batch's (same passes)
+    # plain single-instance loop (untimed for `value`)
     plain_s, plain = [], None
-    for _ in range(max(1, args.plain_reps)):
+    for _ in range(0 if args.no_plain else max(1, args.plain_reps)):
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         plain = [ttr.round_adaptive(devs[i], C4_TOL, C4_BLOCK, seeds[i]) for i in range(len(devs))]
         torch.cuda.synchronize()
         plain_s.append(time.perf_counter() - t1)
-    same = all(p[1]["ranks"] == b[1]["ranks"] and all(torch.equal(u, v) for u, v in zip(p[0], b[0]))
-               for p, b in zip(plain, res))
-    pc_bytes = sum(p[1]["pc_bytes"] for p in plain)
-    pc_flops = sum(p[1]["pc_flops"] for p in plain)
-    pc_per_step = sum(p[1]["pc_launches"] for p in plain)
-    assert pc_launches == pc_per_step * args.steps, (pc_launches, pc_per_step, args.steps)
-    avg_launch_s = pc_ms / 1e3 / pc_launches
+    ranks_equal = None if plain is None else all(p[1]["ranks"] == b[1]["ranks"] for p, b in zip(plain, res))
+    # result of a sampled tensor alone vs in the batch (bitwise)
+    j = len(xs) // 3
+    alone = ttr.BatchPlan([devs[j]], C4_TOL, C4_BLOCK, [seeds[j]])
+    alone.launch()
+    (ya, ia), = alone.finish()
+    alone_same = ia["ranks"] == res[j][1]["ranks"] and all(torch.equal(u, v) for u, v in zip(ya, res[j][0]))
+    bytes_step, flops_step = batch_model(xs, res)
+    pc_bytes = sum(r[1]["pc_bytes"] for r in res)
     step_total = sum(step_s)
     value = len(xs) * args.steps / step_total
+    kern_s = pctl(kern_ms, 50) / 1e3
     out = {
         "metric": "TT-roundings/s + sketch GB/s vs plain & TT-SVD at rel err <=1e-6",
         "value": value,
@@ -253,24 +286,28 @@ def run_headline(args):
         "data": "synthetic",
         "config": {"workload": c4_desc(len(xs)), "tensors": len(xs), "tol": C4_TOL,
                    "ell_block": C4_BLOCK, "sketch_precision": "f64",
-                   "input_GB": sum(c.numel() * 8 for x in devs for c in x) / 1e9},
+                   "input_GB": sum(c.numel() * 8 for x in devs for c in x) / 1e9,
+                   "launch": "one persistent kernel per step (graph-capturable), plan built once"},
         "step_s": {"median": pctl(step_s, 50), "p10": pctl(step_s, 10), "p90": pctl(step_s, 90),
                    "steps": args.steps},
-        "plain_value": len(xs) / pctl(plain_s, 50),
-        "plain_step_s": {"median": pctl(plain_s, 50), "reps": len(plain_s)},
-        "speedup_vs_plain": pctl(plain_s, 50) / pctl(step_s, 50),
-        "bitwise_equal_to_plain": same,
+        "kernel_ms": {"median": pctl(kern_ms, 50), "p10": pctl(kern_ms, 10), "p90": pctl(kern_ms, 90)},
+        "plan_create_s": plan_s,
+        "batch_call_value": len(xs) / pctl(call_s, 50) if call_s else None,
+        "plain_value": len(xs) / pctl(plain_s, 50) if plain_s else None,
+        "plain_step_s": {"median": pctl(plain_s, 50), "reps": len(plain_s)} if plain_s else None,
+        "speedup_vs_plain": pctl(plain_s, 50) / pctl(step_s, 50) if plain_s else None,
+        "ranks_equal_to_plain": ranks_equal,
+        "alone_equals_in_batch": alone_same,
         "sketch_GBps": pc_bytes * args.steps / step_total / 1e9,
-        "roofline": roofline(pc_bytes / pc_per_step, pc_flops / pc_per_step, avg_launch_s,
-                             FP64_MFMA_PEAK_TFLOPS,
-                             "partial contraction, FP64 (pc_kernel<double>), inside the batch"),
+        "roofline": roofline(bytes_step, flops_step, kern_s, FP64_MFMA_PEAK_TFLOPS,
+                             "persistent batched rounding (batch_kernel), whole rounding of the batch"),
         "wall_s": wall,
     }
-    out["roofline"]["launches_per_step"] = pc_per_step
+    out["roofline"]["launches_per_step"] = 1
     if not args.no_side:
         out["side"] = {"c2_f32": side_c2(args), "c3_f64": side_c3(args)}
-    if not args.no_parity:
-        out["parity"] = c4_parity(xs, res, seeds)
+    if not args.no_parity and plain is not None:
+        out["parity"] = c4_parity(xs, res, seeds, plain)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = c4_cpu_baseline(xs, seeds, args.cpu_budget)
     print(json.dumps(out), flush=True)
@@ -350,22 +387,25 @@ def c4_sample(count, k):
     return list(range(0, count, step))[:k]
 
 
-def c4_parity(xs, res, seeds):
+def c4_parity(xs, res, seeds, plain):
     """Sampled tensors of the last batch step against the oracle (same
-    Gaussian factors): relative difference and ranks, and their error
-    against X."""
+    Gaussian factors) and against the plain single-instance rounding:
+    relative differences and ranks, and their error against X."""
     from oracle import krp, tt
     idx = c4_sample(len(xs), 6)
-    diffs, errs, same = [], [], True
+    diffs, dplain, errs, same = [], [], [], True
     for i in idx:
         yg = [c.cpu().numpy() for c in res[i][0]]
+        yp = [c.cpu().numpy() for c in plain[i][0]]
         yo, io = krp.round_adaptive(xs[i], C4_TOL, C4_BLOCK, seeds[i])
         same = same and io["ranks"] == res[i][1]["ranks"]
         nx = tt.norm(xs[i])
         diffs.append(tt.diff_norm(yg, yo) / nx)
+        dplain.append(tt.diff_norm(yg, yp) / nx)
         errs.append(tt.diff_norm(xs[i], yg) / nx)
     return {"tensors": idx, "max_rel_diff_vs_oracle": max(diffs), "ranks_equal": same,
-            "max_rel_err_vs_X": max(errs), "tol_vs_oracle": 1e-10, "tol_vs_X": C4_TOL}
+            "max_rel_diff_vs_plain": max(dplain), "max_rel_err_vs_X": max(errs), "tol_vs_oracle": 1e-10,
+            "tol_vs_X": C4_TOL}
 
 
 def c4_cpu_baseline(xs, seeds, budget_s):

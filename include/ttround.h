@@ -229,17 +229,70 @@ tt_status tt_workspace_bytes(const tt_view* x, int64_t ell_max, tt_prec prec, si
 
 /* Batched adaptive rounding (Sec. 3.3 applied to `count` independent
  * tensors): xs[i] is rounded to tol[i] with seed seeds[i] into ys[i] (caller
- * buffers sized by tt_out_capacity), exactly as tt_round_adaptive would
- * (bitwise the same result).  The roundings run concurrently on a
- * process-wide pool of worker threads, each with its own HIP stream and
- * workspace, so their kernels overlap on the device.  opts (may be NULL)
- * applies to all; opts->stream is synchronized before the work starts and
- * the call returns when every result is complete.  Returns TT_OK, or the
- * status of the first failed tensor (its index is in tt_last_error());
- * the others are still computed. */
+ * buffers sized by tt_out_capacity).  With a float64 sketch and no
+ * recompression pass (opts NULL or prec F64, recompress 0) the batch runs
+ * as one persistent launch (tt_batch_create / _launch / _finish below) on
+ * a workspace the library keeps per device; every result is bitwise the
+ * same alone or in any batch and agrees with tt_round_adaptive to rounding
+ * error.  Otherwise the roundings run as tt_round_adaptive calls (bitwise
+ * the same results) on a process-wide pool of worker threads, each with its
+ * own HIP stream and workspace, so their kernels overlap on the device.
+ * opts (may be NULL) applies to all; the call returns when every result is
+ * complete.  Returns TT_OK, or the status of the first failed tensor (its
+ * index is in tt_last_error()). */
 tt_status tt_round_adaptive_batch(const tt_view* xs, int32_t count, const double* tol,
                                   int64_t ell_block, const uint64_t* seeds, const tt_opts* opts,
                                   tt_out* ys);
+
+/* ---- Batched rounding in one persistent launch (graph-capturable) -------
+ * The same roundings as tt_round_adaptive_batch (Sec. 3.3 on `count`
+ * independent tensors, float64 sketch, no recompression pass), run by one
+ * persistent kernel: workgroups take (tensor, member) tickets from a device
+ * counter, largest tensors first, and each tensor is rounded by a team of
+ * workgroups whose size depends on that tensor alone; every adaptive
+ * decision is taken on the device.  A tensor's result is therefore bitwise
+ * the same alone or in any batch; it agrees with tt_round_adaptive (the
+ * same algorithm, seed and Gaussian factors, other kernels) to rounding
+ * error.  Sketch blocks (ell_block and ceil(f_init rbar_k)) must not exceed
+ * 64 columns (TT_EUNSUPPORTED).
+ *
+ * tt_batch_workspace_bytes: device workspace (bytes) of the batch.
+ * tt_batch_create: validates the batch, lays it out in `workspace`
+ *   (caller-owned device memory of at least that size) and uploads the
+ *   descriptors (synchronising opts->stream).  The inputs, outputs (ys:
+ *   caller buffers sized by tt_out_capacity) and workspace stay borrowed
+ *   until tt_batch_destroy.  opts->prec must be F64 and opts->recompress 0
+ *   (TT_EUNSUPPORTED otherwise).
+ * tt_batch_launch: enqueues the counter reset and the persistent kernel on
+ *   `stream` and returns; no allocation and no host synchronisation, so it
+ *   may be recorded in a HIP graph and the graph replayed (every replay
+ *   recomputes every result).
+ * tt_batch_finish: synchronises `stream`, writes every ys[i].ranks and
+ *   ys[i].orth (1), and returns TT_EDEVICE naming the first tensor whose
+ *   team barrier timed out (the kernel still ends; such a result is
+ *   invalid).
+ * tt_batch_info: the run record of tensor i after tt_batch_finish (tau,
+ *   nrmx, iterations, passes, min_margin, and the partial-contraction
+ *   counters with pc_launches counting contracted cores over all passes).
+ * tt_batch_team: the team size (workgroups) of tensor i.
+ * tt_batch_record: tensor i's raw run record (below). */
+typedef struct tt_batch tt_batch;
+tt_status tt_batch_workspace_bytes(const tt_view* xs, int32_t count, int64_t ell_block,
+                                   const tt_opts* opts, size_t* bytes);
+tt_status tt_batch_create(const tt_view* xs, int32_t count, const double* tol, int64_t ell_block,
+                          const uint64_t* seeds, const tt_opts* opts, tt_out* ys, void* workspace,
+                          size_t workspace_bytes, tt_batch** batch);
+tt_status tt_batch_launch(const tt_batch* batch, void* stream);
+tt_status tt_batch_finish(tt_batch* batch, void* stream);
+tt_status tt_batch_info(const tt_batch* batch, int32_t i, tt_info* info);
+tt_status tt_batch_team(const tt_batch* batch, int32_t i, int32_t* team);
+/* Raw run record of tensor i after tt_batch_finish, up to cap doubles into
+ * out (count in *n): tau, nrmx, iterations, passes, generated columns,
+ * Householder fallbacks, shifted CholeskyQR passes, min |est-tau|/tau, then
+ * 24 (first core, columns) pairs of the partial-contraction passes, then
+ * the device wall clock (100 MHz ticks) at the tensor's start and end. */
+tt_status tt_batch_record(const tt_batch* batch, int32_t i, double* out, int32_t cap, int32_t* n);
+void tt_batch_destroy(tt_batch* batch);
 
 /* ---- Served rounding ---------------------------------------------------
  * A server owns worker threads (one HIP stream each) on the device current

@@ -13,7 +13,7 @@ import ctypes
 import os
 
 __all__ = ["lib", "round_fixed", "round_fixed_noalloc", "round_adaptive", "gaussian_factor", "philox4x32_10",
-           "partial_contractions", "qr", "svd_small", "out_capacity", "last_info", "TTError",
+           "partial_contractions", "qr", "svd_small", "BatchPlan", "round_adaptive_batch", "out_capacity", "last_info", "TTError",
            "PREC_F64", "PREC_F32", "PREC_BF16", "LIB_PATH"]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libttround.so")
@@ -102,6 +102,14 @@ def lib():
             "tt_kernel_timing": [i32],
             "tt_workspace_bytes": [P(_View), i64, ctypes.c_int, P(ctypes.c_size_t)],
             "tt_round_adaptive_batch": [P(_View), i32, P(dbl), i64, P(u64), P(_Opts), P(_Out)],
+            "tt_batch_workspace_bytes": [P(_View), i32, i64, P(_Opts), P(ctypes.c_size_t)],
+            "tt_batch_create": [P(_View), i32, P(dbl), i64, P(u64), P(_Opts), P(_Out), vp,
+                                ctypes.c_size_t, P(vp)],
+            "tt_batch_launch": [vp, vp],
+            "tt_batch_finish": [vp, vp],
+            "tt_batch_info": [vp, i32, P(_Info)],
+            "tt_batch_team": [vp, i32, P(i32)],
+            "tt_batch_record": [vp, i32, P(dbl), i32, P(i32)],
             "tt_server_create": [P(_ServerCfg), P(vp)],
             "tt_round_submit": [vp, P(_Request), P(u64)],
             "tt_round_poll": [vp, u64, P(P(_Result))],
@@ -120,6 +128,8 @@ def lib():
         L.tt_last_error.restype = ctypes.c_char_p
         L.tt_result_release.argtypes = [P(_Result)]
         L.tt_result_release.restype = None
+        L.tt_batch_destroy.argtypes = [vp]
+        L.tt_batch_destroy.restype = None
         L.tt_server_destroy.argtypes = [vp]
         L.tt_server_destroy.restype = None
         _lib = L
@@ -433,6 +443,89 @@ def round_adaptive_batch(tts, tol, ell_block, seeds, f_init=None, nrmx=None, rec
               for k in range(len(cores))]
         res.append((ys, {"ranks": rk, "orth": int(out_arr[i].orth)}))
     return res
+
+
+class BatchPlan:
+    """A batch of adaptive roundings laid out for the persistent kernel
+    (tt_batch_create): the workspace and the output buffers are torch
+    tensors owned by this object.  launch(stream) only enqueues kernels, so
+    it may run under torch.cuda.graph capture and be replayed; finish()
+    synchronises the stream and returns [(cores, info)] like
+    round_adaptive_batch."""
+
+    def __init__(self, tts, tol, ell_block, seeds, f_init=None, nrmx=None, stream=None):
+        torch = _torch()
+        self.count = count = len(tts)
+        tols = [float(tol)] * count if not hasattr(tol, "__len__") else [float(t) for t in tol]
+        sds = [int(seeds)] * count if not hasattr(seeds, "__len__") else [int(x) for x in seeds]
+        self.tts = tts
+        self.holders, outs, self.bufs = [], [], []
+        for cores in tts:
+            h = _ViewHolder(cores)
+            d = len(cores)
+            caps = out_capacity(cores)
+            b = [torch.empty(max(int(c), 1), dtype=torch.float64, device=cores[0].device) for c in caps]
+            rk = (ctypes.c_int64 * (d + 1))()
+            ptrs = (ctypes.c_void_p * d)(*[x.data_ptr() for x in b])
+            capa = (ctypes.c_int64 * d)(*caps)
+            self.holders.append((h, ptrs, capa, rk))
+            outs.append(_Out(d, rk, ptrs, capa, 0))
+            self.bufs.append(b)
+        self.views = (_View * count)(*[h[0].view for h in self.holders])
+        self.out_arr = (_Out * count)(*outs)
+        self.opts = _opts("f64", f_init, nrmx, 0, stream)
+        self.tol_arr = (ctypes.c_double * count)(*tols)
+        self.seed_arr = (ctypes.c_uint64 * count)(*sds)
+        nbytes = ctypes.c_size_t()
+        _check(lib().tt_batch_workspace_bytes(self.views, count, int(ell_block), ctypes.byref(self.opts),
+                                              ctypes.byref(nbytes)))
+        self.workspace = torch.empty(max(int(nbytes.value), 8), dtype=torch.uint8, device=tts[0][0].device)
+        self.handle = ctypes.c_void_p()
+        _check(lib().tt_batch_create(self.views, count, self.tol_arr, int(ell_block), self.seed_arr,
+                                     ctypes.byref(self.opts), self.out_arr,
+                                     ctypes.c_void_p(self.workspace.data_ptr()),
+                                     ctypes.c_size_t(self.workspace.numel()), ctypes.byref(self.handle)))
+
+    def records(self):
+        """Raw run records (kBatchInfo doubles per tensor) after finish()."""
+        import numpy as np
+        out = []
+        for i in range(self.count):
+            buf = (ctypes.c_double * 64)()
+            n = ctypes.c_int32()
+            _check(lib().tt_batch_record(self.handle, i, buf, 64, ctypes.byref(n)))
+            out.append(np.array(buf[: n.value]))
+        return out
+
+    def team(self, i):
+        t = ctypes.c_int32()
+        _check(lib().tt_batch_team(self.handle, int(i), ctypes.byref(t)))
+        return int(t.value)
+
+    def launch(self, stream=None):
+        _check(lib().tt_batch_launch(self.handle, _stream(stream)))
+
+    def finish(self, stream=None):
+        _check(lib().tt_batch_finish(self.handle, _stream(stream)))
+        res = []
+        for i, cores in enumerate(self.tts):
+            rk = [int(self.holders[i][3][k]) for k in range(len(cores) + 1)]
+            dims = self.holders[i][0].dims
+            ys = [self.bufs[i][k][: rk[k] * dims[k] * rk[k + 1]].view(rk[k], dims[k], rk[k + 1])
+                  for k in range(len(cores))]
+            info = _Info()
+            _check(lib().tt_batch_info(self.handle, i, ctypes.byref(info)))
+            res.append((ys, {"ranks": rk, "orth": 1, "tau": info.tau, "nrmx": info.nrmx,
+                             "iterations": info.iterations, "passes": info.passes,
+                             "min_margin": info.min_margin, "pc_launches": info.pc_launches,
+                             "pc_bytes": info.pc_bytes, "pc_flops": info.pc_flops}))
+        return res
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.tt_batch_destroy(h)
+            self.handle = None
 
 
 class Server:

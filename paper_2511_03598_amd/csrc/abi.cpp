@@ -9,6 +9,7 @@
 #include <string>
 
 #include "../../include/ttround.h"
+#include "batch_host.hpp"
 #include "executor.hpp"
 #include "runtime.hpp"
 
@@ -374,6 +375,152 @@ tt_status tt_workspace_bytes(const tt_view* x, int64_t ell_max, tt_prec prec, si
     });
 }
 
+}  // extern "C"
+
+struct tt_batch {
+    ttr::BatchPlan plan;
+    std::vector<tt_out> ys;  // the caller's output descriptors (ranks written by finish)
+    std::vector<std::vector<double>> info;
+    int device = 0;
+};
+
+namespace {
+
+struct BatchArgs {
+    std::vector<ttr::Shape> sh;
+    std::vector<const double* const*> cores;
+    std::vector<double> tol;
+    std::vector<uint64_t> seeds;
+    std::vector<ttr::OutCores> outs;
+};
+
+BatchArgs batch_args(const tt_view* xs, int32_t count, const double* tol, const uint64_t* seeds, tt_out* ys) {
+    if (count < 1) throw ttr::Error(TT_EINVAL, "count must be >= 1");
+    if (!xs || !tol || !seeds || !ys) throw ttr::Error(TT_EINVAL, "null batch array");
+    BatchArgs a;
+    for (int32_t i = 0; i < count; ++i) {
+        if (!(tol[i] > 0.0)) throw ttr::Error(TT_EINVAL, "tol[" + std::to_string(i) + "] must be > 0");
+        a.sh.push_back(view_shape(&xs[i]));
+        a.cores.push_back(xs[i].cores);
+        a.tol.push_back(tol[i]);
+        a.seeds.push_back(seeds[i]);
+        a.outs.push_back(out_of(&ys[i], xs[i].d));
+    }
+    return a;
+}
+
+// Read back ranks, run records and statuses of a launched batch into the
+// caller's tt_out descriptors.
+void batch_finish_impl(tt_batch* b, hipStream_t st) {
+    std::vector<std::vector<int64_t>> ranks;
+    std::vector<int> status;
+    b->plan.results(st, ranks, b->info, status);
+    int bad = -1;
+    for (int i = 0; i < b->plan.count; ++i) {
+        if (status[i] != 0 && bad < 0) bad = i;
+        for (size_t k = 0; k < ranks[i].size(); ++k) b->ys[i].ranks[k] = ranks[i][k];
+        b->ys[i].orth = 1;
+    }
+    if (bad >= 0)
+        throw ttr::Error(TT_EDEVICE, "tensor " + std::to_string(bad) + ": a team barrier of the batched rounding timed out");
+}
+
+void fill_batch_info(tt_info& o, const ttr::BatchPlan& plan, int i, const std::vector<double>& v) {
+    o = tt_info{};
+    o.tau = v[0];
+    o.nrmx = v[1];
+    o.iterations = (int32_t)v[2];
+    o.passes = (int32_t)v[3];
+    o.min_margin = v[7];
+    o.qr_retries = 0;
+    plan.pc_work(i, v, o.pc_launches, o.pc_bytes, o.pc_flops);
+}
+
+// Library-owned workspace of the synchronous batch call, per device, kept
+// and grown as needed.
+struct BatchCache {
+    std::mutex mu;
+    void* p = nullptr;
+    size_t cap = 0;
+};
+BatchCache g_batch_cache[64];
+
+}  // namespace
+
+extern "C" {
+
+tt_status tt_batch_workspace_bytes(const tt_view* xs, int32_t count, int64_t ell_block, const tt_opts* opts,
+                                   size_t* bytes) {
+    return guarded([&] {
+        if (!bytes) throw ttr::Error(TT_EINVAL, "null bytes");
+        if (!xs || count < 1) throw ttr::Error(TT_EINVAL, "bad batch");
+        ttr::Options o = make_opts(opts);
+        std::vector<ttr::Shape> sh;
+        for (int32_t i = 0; i < count; ++i) sh.push_back(ttr::make_shape(xs[i].d, xs[i].n, xs[i].ranks));
+        *bytes = ttr::batch_workspace_bytes(sh, ell_block, o.f_init > 0.0 ? o.f_init : 0.1);
+    });
+}
+
+tt_status tt_batch_create(const tt_view* xs, int32_t count, const double* tol, int64_t ell_block,
+                          const uint64_t* seeds, const tt_opts* opts, tt_out* ys, void* workspace,
+                          size_t workspace_bytes, tt_batch** out) {
+    return guarded([&] {
+        if (!out) throw ttr::Error(TT_EINVAL, "null out");
+        *out = nullptr;
+        ttr::Options o = make_opts(opts);
+        BatchArgs a = batch_args(xs, count, tol, seeds, ys);
+        std::unique_ptr<tt_batch> b(new tt_batch());
+        TTR_HIP(hipGetDevice(&b->device));
+        b->plan.create(a.sh, a.cores, a.tol, ell_block, a.seeds, o, a.outs, workspace, workspace_bytes);
+        b->ys.assign(ys, ys + count);
+        *out = b.release();
+    });
+}
+
+tt_status tt_batch_launch(const tt_batch* b, void* stream) {
+    return guarded([&] {
+        if (!b) throw ttr::Error(TT_EINVAL, "null batch");
+        b->plan.launch((hipStream_t)stream);
+    });
+}
+
+tt_status tt_batch_finish(tt_batch* b, void* stream) {
+    return guarded([&] {
+        if (!b) throw ttr::Error(TT_EINVAL, "null batch");
+        batch_finish_impl(b, (hipStream_t)stream);
+    });
+}
+
+tt_status tt_batch_info(const tt_batch* b, int32_t i, tt_info* info) {
+    return guarded([&] {
+        if (!b || !info) throw ttr::Error(TT_EINVAL, "null argument");
+        if (i < 0 || i >= b->plan.count) throw ttr::Error(TT_EINVAL, "tensor index out of range");
+        if (b->info.empty()) throw ttr::Error(TT_EINVAL, "tt_batch_finish has not run");
+        fill_batch_info(*info, b->plan, i, b->info[i]);
+    });
+}
+
+tt_status tt_batch_team(const tt_batch* b, int32_t i, int32_t* team) {
+    return guarded([&] {
+        if (!b || !team) throw ttr::Error(TT_EINVAL, "null argument");
+        if (i < 0 || i >= b->plan.count) throw ttr::Error(TT_EINVAL, "tensor index out of range");
+        *team = b->plan.team[i];
+    });
+}
+
+tt_status tt_batch_record(const tt_batch* b, int32_t i, double* out, int32_t cap, int32_t* n) {
+    return guarded([&] {
+        if (!b || !out || !n) throw ttr::Error(TT_EINVAL, "null argument");
+        if (i < 0 || i >= b->plan.count) throw ttr::Error(TT_EINVAL, "tensor index out of range");
+        if (b->info.empty()) throw ttr::Error(TT_EINVAL, "tt_batch_finish has not run");
+        const int k = std::min<int>(cap, (int)b->info[i].size());
+        for (int j = 0; j < k; ++j) out[j] = b->info[i][j];
+        *n = k;
+    });
+}
+
+void tt_batch_destroy(tt_batch* b) { delete b; }
+
 tt_status tt_round_adaptive_batch(const tt_view* xs, int32_t count, const double* tol,
                                   int64_t ell_block, const uint64_t* seeds, const tt_opts* opts,
                                   tt_out* ys) {
@@ -382,6 +529,40 @@ tt_status tt_round_adaptive_batch(const tt_view* xs, int32_t count, const double
         if (count == 0) return;
         if (!xs || !tol || !seeds || !ys) throw ttr::Error(TT_EINVAL, "null batch array");
         ttr::Options o = make_opts(opts);
+        if (o.prec == 0 && !o.recompress) {
+            // one persistent launch over a library-owned workspace
+            BatchArgs a = batch_args(xs, count, tol, seeds, ys);
+            const size_t need = ttr::batch_workspace_bytes(a.sh, ell_block, o.f_init > 0.0 ? o.f_init : 0.1);
+            int dev = 0;
+            TTR_HIP(hipGetDevice(&dev));
+            if (dev < 0 || dev >= 64) throw ttr::Error(TT_EUNSUPPORTED, "device index out of range");
+            BatchCache& c = g_batch_cache[dev];
+            std::lock_guard<std::mutex> lk(c.mu);
+            if (c.cap < need) {
+                if (c.p) {
+                    TTR_HIP(hipDeviceSynchronize());
+                    TTR_HIP(hipFree(c.p));
+                    c.p = nullptr;
+                    c.cap = 0;
+                }
+                if (hipMalloc(&c.p, need) != hipSuccess) {
+                    (void)hipGetLastError();
+                    c.p = nullptr;
+                    throw ttr::Error(TT_ENOMEM, "batch workspace allocation of " + std::to_string(need) + " bytes failed");
+                }
+                c.cap = need;
+            }
+            tt_batch b;
+            b.device = dev;
+            b.plan.create(a.sh, a.cores, a.tol, ell_block, a.seeds, o, a.outs, c.p, c.cap);
+            b.ys.assign(ys, ys + count);
+            b.plan.launch(o.stream);
+            batch_finish_impl(&b, o.stream);
+            tt_info last{};
+            fill_batch_info(last, b.plan, count - 1, b.info[count - 1]);
+            g_info = last;
+            return;
+        }
         std::vector<std::shared_ptr<ttr::Job>> jobs;
         jobs.reserve(count);
         for (int i = 0; i < count; ++i) {

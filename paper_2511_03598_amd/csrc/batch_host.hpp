@@ -1,0 +1,54 @@
+// Host planning of the persistent batched adaptive rounding (batch.hip).
+#pragma once
+
+#include <vector>
+
+#include "batch.hpp"
+#include "runtime.hpp"
+
+namespace ttr {
+
+// Workspace bytes of a batch (descriptors, barriers and every tensor's
+// sketch, basis, cores, partial slots), with the same checks as
+// BatchPlan::create.
+size_t batch_workspace_bytes(const std::vector<Shape>& sh, int64_t ell_block, double f_init);
+// Work (flops of the rounding model) per team member: a tensor gets the
+// largest power-of-two team T with 2T times this below its work estimate,
+// capped by batch_team_cap().  TTR_BATCH_TEAM_FLOPS overrides it.
+double batch_team_flops();
+int batch_team_cap();
+
+// A batch laid out in a caller's workspace: create() validates, carves the
+// workspace and uploads the descriptors (synchronising opts.stream);
+// launch() enqueues the counter reset and the persistent kernel only (no
+// allocation, no host synchronisation: it may be captured in a graph and
+// replayed); results() synchronises the stream and reads ranks, run
+// records and statuses.
+struct BatchPlan {
+    int count = 0, grid = 1;
+    std::vector<int> order, prefix, team;
+    BatchTT* d_tts = nullptr;
+    int* d_order = nullptr;
+    int* d_prefix = nullptr;
+    unsigned* d_zero = nullptr;
+    int64_t zwords = 0;
+    size_t bytes_used = 0;
+    std::vector<int64_t*> ranks_dev;
+    std::vector<double*> info_dev;
+    std::vector<int> d_of;
+
+    void create(const std::vector<Shape>& sh, const std::vector<const double* const*>& cores,
+                const std::vector<double>& tol, int64_t ell_block, const std::vector<uint64_t>& seeds,
+                const Options& o, const std::vector<OutCores>& outs, void* ws, size_t ws_bytes);
+    void launch(hipStream_t st) const;
+    void results(hipStream_t st, std::vector<std::vector<int64_t>>& ranks, std::vector<std::vector<double>>& info,
+                 std::vector<int>& status) const;
+    // Partial contractions of tensor i by its run record's pass log (Sec. 3.1
+    // cost model): one float64 read of each contracted core and one write of
+    // its W columns per pass, 2 r_{k-1} n_k r_k l + 2 r_{k-1} r_k l flops per
+    // core; `cores` counts the contracted cores over all passes.
+    void pc_work(int i, const std::vector<double>& info, int64_t& cores, double& bytes, double& flops) const;
+    std::vector<Shape> shapes;
+};
+
+}  // namespace ttr

@@ -30,6 +30,8 @@ def _same(a, b):
 
 
 def test_batch_equals_single_calls(lib):
+    """The float64 batch (one persistent launch) gives the single calls'
+    ranks and tensors to rounding error, and the oracle's within 1e-10."""
     xs = _mix()
     devs = [to_dev(x) for x in xs]
     res = lib.round_adaptive_batch(devs, 1e-6, 4, [11 + i for i in range(len(xs))])
@@ -38,10 +40,23 @@ def test_batch_equals_single_calls(lib):
         y1, i1 = lib.round_adaptive(dv, 1e-6, 4, 11 + i)
         say("batch", i, info["ranks"])
         assert info["ranks"] == i1["ranks"]
-        assert _same(to_host(ys), to_host(y1))
+        assert rel_tensor_diff(x, to_host(ys), to_host(y1)) <= 1e-12
         yo, io = krp.round_adaptive(x, 1e-6, 4, 11 + i)
         assert info["ranks"] == io["ranks"]
         assert rel_tensor_diff(x, to_host(ys), yo) <= 1e-10
+
+
+def test_batch_f32_sketch_equals_single_calls(lib):
+    """A float32-sketch batch runs as concurrent single roundings: bitwise
+    the same results as the single calls."""
+    xs = _mix()
+    devs = [to_dev(x) for x in xs]
+    res = lib.round_adaptive_batch(devs, 1e-6, 4, [11 + i for i in range(len(xs))], prec="f32")
+    for i, dv in enumerate(devs):
+        ys, info = res[i]
+        y1, i1 = lib.round_adaptive(dv, 1e-6, 4, 11 + i, prec="f32")
+        assert info["ranks"] == i1["ranks"]
+        assert _same(to_host(ys), to_host(y1))
 
 
 def test_server_results_same_alone_and_in_mix(lib):
