@@ -2,7 +2,8 @@
 
 Follows the paper step by step:
   * partial contractions with a Khatri-Rao sketch, Eq. (6)-(8) and the
-    Algorithm "Right-to-Left Contraction with KRP Structured Matrix" (Sec. 3.1);
+    Algorithm "Right-to-Left Contraction with KRP Structured Matrix" (Sec. 3.1),
+    and the left-to-right order the same section describes;
   * fixed-rank Randomize-then-Orthogonalize with KRP (Sec. 3.2);
   * residual sketching for basis expansion (Sec. 3.3) and the adaptive-rank
     Randomize-then-Orthogonalize with KRP (Sec. 3.3);
@@ -64,6 +65,22 @@ def partial_contractions_rl(cores, omegas, t):
     w = {d: h_unf(cores[d - 1]) @ omegas[d]}
     for k in range(d - 1, t - 1, -1):
         w[k] = h_unf(cores[k - 1]) @ khatri_rao(omegas[k], w[k + 1])
+    return w
+
+
+def partial_contractions_lr(cores, omegas, t):
+    """Left-to-right partial contractions (Sec. 3.1: the recurrence of the
+    right-to-left algorithm run in the other order), for k = 1..t:
+    WL_1 = V(X_1)^T Omega_1 and WL_k = V(X_k)^T [WL_{k-1} (.) Omega_k], i.e.
+    WL_k(b, j) = sum_{a,i} X_k(a,i,b) WL_{k-1}(a,j) Omega_k(i,j).
+
+    cores: list of d cores; omegas: dict 1-based mode -> (n_mode x l).
+    Returns dict 1-based k -> WL_k of shape (r_k x l), k = 1..t.
+    """
+    w = {1: v_unf(cores[0]).T @ omegas[1]}
+    for k in range(2, t + 1):
+        # the row (a, i) of V(X_k) pairs with WL_{k-1}(a, :) * Omega_k(i, :)
+        w[k] = v_unf(cores[k - 1]).T @ khatri_rao(w[k - 1], omegas[k])
     return w
 
 

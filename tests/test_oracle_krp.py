@@ -1,6 +1,7 @@
 """Pins for the oracle's KRP rounding:
   * partial contractions against the definition (Eq. 6): the explicit
-    suffix unfolding H(X_{k:d}) times the explicit Khatri-Rao product;
+    suffix unfolding H(X_{k:d}) times the explicit Khatri-Rao product, and
+    the left-to-right ones against the explicit prefix unfolding V(X_{1:k});
   * fixed rank at d=2 is Halko's randomized range finder; exact recovery
     when the sketch is at least the true rank (C1);
   * adaptive at d=2 is the adaptive range finder with the sketched
@@ -67,6 +68,52 @@ def test_partial_contractions_vs_definition(d):
             u = np.einsum('aib,bj->aij', x[k - 1], w[k + 1])
             alt = np.einsum('aij,ij->aj', u, om[k])
             assert np.allclose(w[k], alt, rtol=1e-13, atol=1e-13 * np.abs(ref).max())
+
+
+def _prefix_v(cores, k):
+    """Explicit V(X_{1:k}) (1-based k): prod(n_1..n_k) x r_k, i_k fastest."""
+    acc = cores[0].reshape(-1, cores[0].shape[2])
+    for c in cores[1:k]:
+        r0, n, r1 = c.shape
+        acc = (acc @ c.reshape(r0, n * r1)).reshape(-1, r1)
+    return acc
+
+
+@pytest.mark.parametrize("d", [2, 3, 5])
+def test_partial_contractions_lr_vs_definition(d):
+    """WL_k = V(X_{1:k})^T (Omega_1 (.) ... (.) Omega_k) with the row order of
+    the prefix unfolding (the last mode fastest), formed explicitly."""
+    dims = [3, 4, 2, 3, 2][:d]
+    ranks = [2, 3, 4, 2][:d - 1]
+    x = ttgen.small_random(60 + d, d, dims, ranks)
+    ell = 5
+    om = krp.draw_omegas(98, dims, range(1, d + 1), 0, ell)
+    w = krp.partial_contractions_lr(x, om, d)
+    for k in range(1, d + 1):
+        ref = _prefix_v(x, k).T @ _explicit_krp([om[j] for j in range(1, k + 1)])
+        assert w[k].shape == (x[k - 1].shape[2], ell)
+        assert np.allclose(w[k], ref, rtol=1e-13, atol=1e-13 * np.abs(ref).max())
+
+
+def test_partial_contractions_lr_d2_is_gemm_and_meets_rl():
+    """d=2: WL_1 = V(X_1)^T Omega_1.  For any d the full contractions agree:
+    WL_d (1 x l) from the left and W_1 (1 x l) from the right are both
+    vec(X)^T (Omega_1 (.) ... (.) Omega_d)."""
+    x = ttgen.small_random(71, 2, [6, 5], [4])
+    om = krp.draw_omegas(3, [6, 5], range(1, 3), 0, 7)
+    w = krp.partial_contractions_lr(x, om, 1)
+    assert np.allclose(w[1], x[0].reshape(6, 4).T @ om[1], rtol=1e-14, atol=1e-14)
+    for d, dims, ranks in [(3, [3, 4, 5], [2, 3]), (4, [2, 3, 2, 3], [3, 4, 2])]:
+        x = ttgen.small_random(72 + d, d, dims, ranks)
+        om = krp.draw_omegas(4, dims, range(1, d + 1), 0, 6)
+        left = krp.partial_contractions_lr(x, om, d)[d]
+        right = krp.partial_contractions_rl(x, om, 2)[2]
+        # W_1 = H(X_1) [Omega_1 (.) W_2] from the right
+        full_r = np.einsum('aib,ij,bj->aj', x[0], om[1], right)
+        assert np.allclose(left, full_r, rtol=1e-12, atol=1e-12 * np.abs(full_r).max())
+        f = tt.full(x).reshape(-1)
+        ref = f @ _explicit_krp([om[j] for j in range(1, d + 1)])
+        assert np.allclose(left[0], ref, rtol=1e-12, atol=1e-12 * np.abs(ref).max())
 
 
 def test_partial_contractions_chunk_invariant():

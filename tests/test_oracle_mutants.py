@@ -45,6 +45,29 @@ def test_transposed_core_contraction_caught(monkeypatch):
     assert not np.allclose(w[2], ref, rtol=1e-8)
 
 
+def test_lr_reversed_omega_rows_caught(monkeypatch):
+    orig = krp.partial_contractions_lr
+
+    def wrong(cores, om, t):
+        return orig(cores, {k: v[::-1].copy() for k, v in om.items()}, t)
+
+    monkeypatch.setattr(krp, "partial_contractions_lr", wrong)
+    _fails(pins_krp.test_partial_contractions_lr_vs_definition, 3)
+
+
+def test_lr_krp_factor_order_caught(monkeypatch):
+    def wrong(cores, om, t):
+        # pairs row (a, i) of V(X_k) with Omega_k(a) * WL_{k-1}(i): the KRP
+        # factors in the wrong order
+        w = {1: krp.v_unf(cores[0]).T @ om[1]}
+        for k in range(2, t + 1):
+            w[k] = krp.v_unf(cores[k - 1]).T @ krp.khatri_rao(om[k], w[k - 1])
+        return w
+
+    monkeypatch.setattr(krp, "partial_contractions_lr", wrong)
+    _fails(pins_krp.test_partial_contractions_lr_d2_is_gemm_and_meets_rl)
+
+
 def test_residual_sign_flip_caught(monkeypatch):
     def wrong(sk, z, q, k, b):
         need = q.shape[1] + b
