@@ -206,6 +206,20 @@ tt_status tt_philox4x32_10(const uint32_t* ctr, const uint32_t* key, uint32_t* o
 tt_status tt_partial_contractions(const tt_view* x, uint64_t seed, int64_t col0, int64_t ncols,
                                   int32_t t, tt_prec prec, double* const* w, void* stream);
 
+/* Left-to-right KRP partial contractions (Sec. 3.1, the same recurrence
+ * run from the first core): W^L_1 = V(X_1)^T Omega_1 and
+ * W^L_k(b, c) = sum_{a,i} X_k(a, i, b) W^L_{k-1}(a, c) Omega_k(i, c), i.e.
+ * W^L_k = V(X_k)^T [W^L_{k-1} (.) Omega_k], for k = 1..t (1 <= t <= d),
+ * over sketch columns [col0, col0+ncols) of the factors drawn from `seed`
+ * (the columns tt_gaussian_factor returns).  FP64 throughout.  w[k-1] is a
+ * caller-owned device float64 buffer for W^L_k of shape r_k x ncols,
+ * row-major (ld = ncols), k = 1..t; each W^L_k is read back as the operand
+ * of the next core, so the buffers must not overlap.  Blocks until the
+ * results are written.  TT_EINVAL for t outside [1, d], an empty or
+ * negative column range or a null buffer. */
+tt_status tt_partial_contractions_lr(const tt_view* x, uint64_t seed, int64_t col0, int64_t ncols,
+                                     int32_t t, double* const* w, void* stream);
+
 /* Thin QR with diag(R) >= 0 of an m x b column-major float64 device matrix
  * a (ld = m), m >= b >= 1, b <= 64: on return a holds Q (explicit).  The
  * same routine the rounding uses for its sketches. */

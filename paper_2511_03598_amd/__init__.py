@@ -97,6 +97,7 @@ def lib():
             "tt_gaussian_factor": [u64, i32, i64, i64, i64, vp, vp],
             "tt_philox4x32_10": [vp, vp, vp, i64, vp],
             "tt_partial_contractions": [P(_View), u64, i64, i64, i32, ctypes.c_int, P(vp), vp],
+            "tt_partial_contractions_lr": [P(_View), u64, i64, i64, i32, P(vp), vp],
             "tt_qr": [vp, i64, i64, vp],
             "tt_svd_small": [vp, i64, i64, vp, vp, vp, dbl, i64, P(i64), vp],
             "tt_kernel_timing": [i32],
@@ -344,6 +345,23 @@ def partial_contractions(cores, seed, col0, ncols, t=2, prec="f64", stream=None)
     arr = (ctypes.c_void_p * len(ws))(*[w.data_ptr() for w in ws])
     _check(lib().tt_partial_contractions(ctypes.byref(h.view), ctypes.c_uint64(seed), int(col0),
                                          int(ncols), int(t), _PREC[prec], arr, _stream(stream)))
+    return ws
+
+
+def partial_contractions_lr(cores, seed, col0, ncols, t=None, stream=None):
+    """Left-to-right contractions W^L_1..W^L_t (t defaults to d) over sketch
+    columns [col0, col0+ncols); returns a list of float64 (r_k x ncols)
+    tensors, k = 1..t."""
+    torch = _torch()
+    h = _ViewHolder(cores)
+    d = len(cores)
+    t = d if t is None else int(t)
+    # buffers for the k the library accepts; it rejects t outside [1, d]
+    ws = [torch.empty((h.ranks[k], max(int(ncols), 0)), dtype=torch.float64, device=cores[0].device)
+          for k in range(1, min(t, d) + 1)]
+    arr = (ctypes.c_void_p * max(len(ws), 1))(*[w.data_ptr() for w in ws])
+    _check(lib().tt_partial_contractions_lr(ctypes.byref(h.view), ctypes.c_uint64(seed), int(col0),
+                                            int(ncols), int(t), arr, _stream(stream)))
     return ws
 
 

@@ -16,7 +16,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libttround.so")
 
-SOURCES = ["omega.hip", "partial.hip", "gemm.hip", "util.hip", "qr.hip", "qr_chol.hip", "svd.hip",
+SOURCES = ["omega.hip", "partial.hip", "lr.hip", "gemm.hip", "util.hip", "qr.hip", "qr_chol.hip", "svd.hip",
            "noalloc.hip", "batch.hip", "batch_host.cpp", "runtime.cpp", "executor.cpp", "abi.cpp"]
 
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

@@ -336,6 +336,18 @@ tt_status tt_partial_contractions(const tt_view* x, uint64_t seed, int64_t col0,
     });
 }
 
+tt_status tt_partial_contractions_lr(const tt_view* x, uint64_t seed, int64_t col0, int64_t ncols,
+                                     int32_t t, double* const* w, void* stream) {
+    return guarded([&] {
+        ttr::Shape s = view_shape(x);
+        if (!w) throw ttr::Error(TT_EINVAL, "null W array");
+        if (t < 1 || t > s.d) throw ttr::Error(TT_EINVAL, "t must be in [1, d]");
+        for (int k = 1; k <= t; ++k)
+            if (!w[k - 1]) throw ttr::Error(TT_EINVAL, "null W pointer");
+        ttr::partial_contractions_lr(s, x->cores, seed, col0, ncols, t, w, (hipStream_t)stream);
+    });
+}
+
 tt_status tt_qr(double* a, int64_t m, int64_t b, void* stream) {
     return guarded([&] { ttr::qr_inplace(a, m, b, (hipStream_t)stream); });
 }

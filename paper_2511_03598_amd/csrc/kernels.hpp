@@ -63,6 +63,26 @@ void launch_fill_int(int* p, int value, int64_t count, hipStream_t s);
 void launch_w_export(int prec, const void* w, const int* colexp, int64_t ld, int rows, int c0,
                      int nc, int slices, int64_t sstride, double* out, int64_t ldo, hipStream_t s);
 
+// ---- left-to-right KRP partial contraction of one core (lr.hip) ----------
+// W(b, c) = sum_{a, i} X(a, i, b) Wp(a, c) Om(i, c) for b < r1, c < nc; X is
+// an r0 x n x r1 core (b fastest); Wp == nullptr stands for W^L_0 = 1 (then
+// r0 must be 1).  Split-K slices write partials (splits x r1 x nc doubles).
+struct LrArgs {
+    const double* X;
+    int r0, n, r1;
+    const double* Wp;  // Wp(a, c) at Wp[a * ldw + c]
+    int64_t ldw;
+    const double* Om;  // Om(i, c) at Om[i * ldo + c]
+    int64_t ldo;
+    double* W;         // W(b, c) at W[b * ldwo + c]
+    int64_t ldwo;
+    int nc;
+};
+// K slices launch_lr uses for one core; the caller provides
+// splits * r1 * nc doubles of partials when this exceeds 1.
+int lr_splits(int r0, int n, int r1, int nc);
+void launch_lr(const LrArgs& g, int splits, double* partials, hipStream_t s);
+
 // ---- general float64 MFMA GEMM (gemm.hip) ----------------------------------
 // C(m,n) = alpha * sum_k A(m,k) B(k,n) + beta * C(m,n), with arbitrary
 // element strides.  B may instead be float storage Bf or bfloat16 storage

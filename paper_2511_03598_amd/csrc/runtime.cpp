@@ -1074,6 +1074,63 @@ void partial_contractions(const Shape& s, const double* const* cores, uint64_t s
     TTR_HIP(hipStreamSynchronize(st));
 }
 
+// W^L_1..W^L_t of the left-to-right recurrence: Omega_1..Omega_t in one
+// launch, then one fused contraction per core (lr.hip), each reading the
+// previous core's output.
+void partial_contractions_lr(const Shape& s, const double* const* cores, uint64_t seed, int64_t col0,
+                             int64_t ncols, int t, double* const* w, hipStream_t st) {
+    if (t < 1 || t > s.d) throw Error(-1, "t must be in [1, d]");
+    if (ncols < 1 || col0 < 0) throw Error(-1, "bad column range");
+    if (ncols > (int64_t)1 << 20) throw Error(-1, "column range too large");
+    WsLease lease(st);
+    Workspace& ws = *lease.ws;
+    std::vector<int64_t> hn(t), ho(t);
+    int64_t total = 0, maxn = 1;
+    size_t part = 0;
+    for (int k = 1; k <= t; ++k) {
+        hn[k - 1] = s.n[k - 1];
+        ho[k - 1] = total;
+        total += s.n[k - 1] * ncols;
+        maxn = std::max(maxn, s.n[k - 1]);
+        const int sp = lr_splits((int)s.r[k - 1], (int)s.n[k - 1], (int)s.r[k], (int)ncols);
+        if (sp > 1) part = std::max(part, (size_t)sp * s.r[k] * ncols);
+    }
+    int64_t* dn = ws.dn.as<int64_t>(t);
+    int64_t* doff = ws.doff.as<int64_t>(t);
+    TTR_HIP(hipMemcpyAsync(dn, hn.data(), t * sizeof(int64_t), hipMemcpyHostToDevice, st));
+    TTR_HIP(hipMemcpyAsync(doff, ho.data(), t * sizeof(int64_t), hipMemcpyHostToDevice, st));
+    double* om = ws.omega.as<double>(total);
+    OmegaArgs oa{};
+    oa.seed = seed;
+    oa.first_mode = 1;
+    oa.n = dn;
+    oa.off = doff;
+    oa.base = om;
+    oa.ld = ncols;
+    oa.col0 = col0;
+    oa.store_col0 = 0;
+    oa.ncols = ncols;
+    launch_omega(oa, t, maxn, st);
+    double* partials = part ? ws.part.as<double>(part) : nullptr;
+    for (int k = 1; k <= t; ++k) {
+        LrArgs g{};
+        g.X = cores[k - 1];
+        g.r0 = (int)s.r[k - 1];
+        g.n = (int)s.n[k - 1];
+        g.r1 = (int)s.r[k];
+        g.Wp = k > 1 ? w[k - 2] : nullptr;
+        g.ldw = ncols;
+        g.Om = om + ho[k - 1];
+        g.ldo = ncols;
+        g.W = w[k - 1];
+        g.ldwo = ncols;
+        g.nc = (int)ncols;
+        TimedScope ts(KT_PC, st);
+        launch_lr(g, lr_splits(g.r0, g.n, g.r1, g.nc), partials, st);
+    }
+    TTR_HIP(hipStreamSynchronize(st));
+}
+
 void qr_inplace(double* a, int64_t m, int64_t b, hipStream_t st) {
     if (!a || m < 1 || b < 1) throw Error(-1, "bad QR request");
     if (m < b) throw Error(-1, "QR needs m >= b");

@@ -88,6 +88,8 @@ void gaussian_factor(uint64_t seed, int mode, int64_t n, int64_t col0, int64_t n
                      hipStream_t st);
 void partial_contractions(const Shape& s, const double* const* cores, uint64_t seed, int64_t col0,
                           int64_t ncols, int t, int prec, double* const* w, hipStream_t st);
+void partial_contractions_lr(const Shape& s, const double* const* cores, uint64_t seed, int64_t col0,
+                             int64_t ncols, int t, double* const* w, hipStream_t st);
 void qr_inplace(double* a, int64_t m, int64_t b, hipStream_t st);
 int64_t svd_small(const double* a, int64_t p, int64_t q, double* g, double* v, double* sig,
                   double tau, int64_t target, hipStream_t st);

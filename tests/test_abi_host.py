@@ -19,7 +19,7 @@ def declared_symbols():
 def test_header_declares_the_boundary():
     names = set(declared_symbols())
     for n in ("tt_round_fixed", "tt_round_adaptive", "tt_out_capacity", "tt_last_error",
-              "tt_partial_contractions", "tt_gaussian_factor", "tt_qr", "tt_philox4x32_10"):
+              "tt_partial_contractions", "tt_partial_contractions_lr", "tt_gaussian_factor", "tt_qr", "tt_philox4x32_10"):
         assert n in names
 
 

@@ -99,6 +99,82 @@ def test_partial_contractions_c2_full_size(lib, prec, tol):
     _pc_case(ttgen.c2(), 42, 0, 60, 2, prec, tol)
 
 
+def _lr_case(x, seed, col0, ncols, t, tol=1e-12):
+    """Every entry of W^L_k is a sum of products that can cancel (at k = d,
+    r_d = 1, it is the sketch of the whole tensor), so the bar is the
+    forward-error bound of such sums: |GPU - oracle| against the same
+    recurrence run on |X_k| and |Omega_k|, which bounds the propagated
+    error of the earlier cores as well."""
+    import paper_2511_03598_amd as ttr
+    dims = [c.shape[1] for c in x]
+    om = krp.draw_omegas(seed, dims, range(1, t + 1), col0, ncols)
+    ref = krp.partial_contractions_lr(x, om, t)
+    bound = krp.partial_contractions_lr([np.abs(c) for c in x], {j: np.abs(o) for j, o in om.items()}, t)
+    got = [w.cpu().numpy() for w in ttr.partial_contractions_lr(to_dev(x), seed, col0, ncols, t)]
+    assert len(got) == t
+    for k in range(1, t + 1):
+        g, r = got[k - 1], ref[k]
+        assert g.shape == r.shape, (k, g.shape, r.shape)
+        err = np.abs(g - r) / np.maximum(bound[k], 1e-300)
+        assert np.max(err) <= tol, (k, np.max(err))
+    return got
+
+
+def test_partial_contractions_lr_c1(lib):
+    say("lr C1")
+    x = ttgen.c1()
+    _lr_case(x, 42, 0, 12, len(x))
+    _lr_case(x, 42, 5, 4, 3)
+
+
+def test_partial_contractions_lr_ragged(lib):
+    """Sizes off the tiles: ranks 37/70/65 (row tiles with tails), n=33,
+    67 columns (two column tiles, the second nearly empty), r0*n from 7 to
+    2310 (one chunk to several split-K slices), t=1 and t=d, col0 > 0."""
+    say("lr ragged")
+    x = ttgen.small_random(21, 5, [7, 13, 5, 33, 9], [37, 70, 3, 65])
+    _lr_case(x, 5, 0, 67, 5)
+    _lr_case(x, 5, 11, 1, 1)
+    _lr_case(x, 5, 3, 130, 4)
+
+
+def test_partial_contractions_lr_c2_full_size(lib):
+    """The benchmark's fixed-rank workload (d=20, n=64, formal ranks 200,
+    ell=60), every core."""
+    say("lr C2 full")
+    x = ttgen.c2()
+    _lr_case(x, 42, 0, 60, len(x))
+
+
+def test_partial_contractions_lr_meets_rl_c2(lib):
+    """Both recurrences give the full sketch: for every k the column-wise
+    dot product of W^L_{k-1} with W_k is the same vector (the sketch of the
+    whole tensor), whichever direction produced the two factors."""
+    import paper_2511_03598_amd as ttr
+    say("lr/rl meet C2")
+    x = ttgen.c2()
+    d = len(x)
+    dev = to_dev(x)
+    lr = [w.cpu().numpy() for w in ttr.partial_contractions_lr(dev, 7, 3, 60)]
+    rl = [w.cpu().numpy() for w in ttr.partial_contractions(dev, 7, 3, 60, 2, "f64")]
+    full = lr[d - 1][0]
+    assert lr[d - 1].shape == (1, 60)
+    for k in range(2, d + 1):
+        meet = np.sum(lr[k - 2] * rl[k - 2], axis=0)
+        scale = np.sum(np.abs(lr[k - 2]) * np.abs(rl[k - 2]), axis=0)
+        assert np.max(np.abs(meet - full) / scale) <= 1e-12, k
+
+
+def test_partial_contractions_lr_rejects_bad_t(lib):
+    import paper_2511_03598_amd as ttr
+    dev = to_dev(ttgen.small_random(3, 3, 4, 3))
+    for t in (0, 4):
+        with pytest.raises(ttr.TTError):
+            ttr.partial_contractions_lr(dev, 1, 0, 4, t)
+    with pytest.raises(ttr.TTError):
+        ttr.partial_contractions_lr(dev, 1, 0, 0, 2)
+
+
 @pytest.mark.parametrize("m,b", [(10, 3), (120, 12), (64, 64), (129, 64), (3840, 60), (1000, 17),
                                  (5000, 1), (20000, 16)])
 def test_qr_matches_householder(lib, m, b):
