@@ -10,7 +10,7 @@
 // MFMA f64 16x16x4: a 32 (b) x 64 (c) output tile per 256-thread workgroup,
 // the k range of a workgroup taken in chunks of 64 rows (a, i) of which
 // each wave multiplies a quarter, operands loaded from global memory
-// straight into MFMA layout before the chunk's first MFMA.  The four wave
+// straight into MFMA layout one chunk ahead of its MFMAs.  The four wave
 // tiles are added in LDS in a fixed order; split-K slices are summed by a
 // second kernel in slice order, so results do not depend on timing.
 #include <algorithm>
@@ -24,6 +24,50 @@ constexpr int LR_TM = 32, LR_TN = 64;
 constexpr int LR_DKW = 4;                 // k-steps of 4 per wave and chunk
 constexpr int LR_CHUNK = 16 * LR_DKW;     // rows (a, i) per chunk (4 waves)
 
+// One chunk's operands for this lane: rows (a, i) = kb + 4 (ks0 + t) + lg
+// of V(X_k) (clamped into the slice; copies past it are never multiplied)
+// and the matching Khatri-Rao entries W^L_{k-1}(a, c) Omega_k(i, c).
+struct LrOps {
+    double a[LR_DKW][2], b[LR_DKW][4];
+};
+
+template <bool FIRST>
+__device__ __forceinline__ void lr_load(const LrArgs& g, int kb, int ks0, int kend, const int (&rows)[2],
+                                        const int (&cols)[4], int lg, LrOps& o) {
+#pragma unroll
+    for (int t = 0; t < LR_DKW; ++t) {
+        const int kc = min(kb + 4 * (ks0 + t) + lg, kend - 1);
+        const int a = FIRST ? 0 : (int)((unsigned)kc / (unsigned)g.n);
+        const int i = kc - a * g.n;
+        const double* xr = g.X + (size_t)kc * g.r1;
+        const double* orow = g.Om + (size_t)i * g.ldo;
+#pragma unroll
+        for (int u = 0; u < 2; ++u) o.a[t][u] = xr[rows[u]];
+        if (FIRST) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) o.b[t][j] = orow[cols[j]];
+        } else {
+            const double* wrow = g.Wp + (size_t)a * g.ldw;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) o.b[t][j] = wrow[cols[j]] * orow[cols[j]];
+        }
+    }
+}
+
+// The wave's k-steps [ks0, ks1) of the chunk at kb: its quarter of the
+// chunk's k-steps of 4 rows.
+__device__ __forceinline__ void lr_split(int kb, int kend, int w, int& ks0, int& ks1) {
+    const int nks = (min(kend - kb, LR_CHUNK) + 3) / 4;
+    ks0 = (w * nks) / 4;
+    ks1 = ((w + 1) * nks) / 4;
+}
+
+// Split-K: slice z = blockIdx.z takes rows [z kchunk, (z+1) kchunk) and
+// writes its tile to partials[z] (r1 x nc) for lr_reduce_kernel; without
+// partials the one slice covers every row and writes W directly.  (Summing
+// the slices in the last slice to finish would need a device-wide release
+// per workgroup, an L2 write-back on this chip that costs more than the
+// second launch.)
 template <bool FIRST>
 __global__ void __launch_bounds__(256) lr_kernel(LrArgs g, int kchunk, double* partials) {
     __shared__ double red[2][LR_TM][LR_TN + 1];
@@ -42,43 +86,39 @@ __global__ void __launch_bounds__(256) lr_kernel(LrArgs g, int kchunk, double* p
 #pragma unroll
         for (int j = 0; j < 4; ++j) acc[i][j] = double4_t{0, 0, 0, 0};
 
+    // two chunks in flight: the next chunk's loads are issued before the
+    // current chunk's MFMAs
     const int kbeg = blockIdx.z * kchunk, kend = min(K, kbeg + kchunk);
+    LrOps cur, nxt;
+    int ks0 = 0, ks1 = 0;
+    if (kbeg < kend) {
+        lr_split(kbeg, kend, w, ks0, ks1);
+        lr_load<FIRST>(g, kbeg, ks0, kend, rows, cols, lg, cur);
+    }
     for (int kb = kbeg; kb < kend; kb += LR_CHUNK) {
-        const int nks = (min(kend - kb, LR_CHUNK) + 3) / 4;
-        const int ks0 = (w * nks) / 4, ks1 = ((w + 1) * nks) / 4;
-        double av[LR_DKW][2], bv[LR_DKW][4];
-#pragma unroll
-        for (int t = 0; t < LR_DKW; ++t) {
-            // row (a, i) of V(X_k), clamped into the slice (unused copies are
-            // never multiplied)
-            const int kc = min(kb + 4 * (ks0 + t) + lg, kend - 1);
-            const int a = FIRST ? 0 : (int)((unsigned)kc / (unsigned)g.n);
-            const int i = kc - a * g.n;
-            const double* xr = g.X + (size_t)kc * g.r1;
-            const double* orow = g.Om + (size_t)i * g.ldo;
-#pragma unroll
-            for (int u = 0; u < 2; ++u) av[t][u] = xr[rows[u]];
-            if (FIRST) {
-#pragma unroll
-                for (int j = 0; j < 4; ++j) bv[t][j] = orow[cols[j]];
-            } else {
-                const double* wrow = g.Wp + (size_t)a * g.ldw;
-#pragma unroll
-                for (int j = 0; j < 4; ++j) bv[t][j] = wrow[cols[j]] * orow[cols[j]];
-            }
+        int ns0 = 0, ns1 = 0;
+        const bool more = kb + LR_CHUNK < kend;
+        if (more) {
+            lr_split(kb + LR_CHUNK, kend, w, ns0, ns1);
+            lr_load<FIRST>(g, kb + LR_CHUNK, ns0, kend, rows, cols, lg, nxt);
         }
 #pragma unroll
         for (int t = 0; t < LR_DKW; ++t) {
             const int ks = ks0 + t;
             if (ks < ks1) {  // uniform per wave
                 const bool kok = kb + 4 * ks + lg < kend;
-                const double a0 = kok ? av[t][0] : 0.0, a1 = kok ? av[t][1] : 0.0;
+                const double a0 = kok ? cur.a[t][0] : 0.0, a1 = kok ? cur.a[t][1] : 0.0;
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
-                    acc[0][j] = mfma_f64_16x16x4(a0, bv[t][j], acc[0][j]);
-                    acc[1][j] = mfma_f64_16x16x4(a1, bv[t][j], acc[1][j]);
+                    acc[0][j] = mfma_f64_16x16x4(a0, cur.b[t][j], acc[0][j]);
+                    acc[1][j] = mfma_f64_16x16x4(a1, cur.b[t][j], acc[1][j]);
                 }
             }
+        }
+        if (more) {
+            cur = nxt;
+            ks0 = ns0;
+            ks1 = ns1;
         }
     }
     // wave tiles: (w0 + w2) + (w1 + w3)
@@ -100,17 +140,23 @@ __global__ void __launch_bounds__(256) lr_kernel(LrArgs g, int kchunk, double* p
                 for (int v = 0; v < 4; ++v) red[w - 2][16 * i + mfma_row_f64(lg, v)][16 * j + li] += acc[i][j][v];
     }
     __syncthreads();
+    constexpr int E = (LR_TM * LR_TN) / 256;
+    if (!partials) {
 #pragma unroll
-    for (int e = 0; e < (LR_TM * LR_TN) / 256; ++e) {
+        for (int e = 0; e < E; ++e) {
+            const int idx = threadIdx.x + 256 * e, r = idx / LR_TN, c = idx % LR_TN;
+            const int row = m0 + r, col = n0 + c;
+            if (row < g.r1 && col < g.nc) g.W[(size_t)row * g.ldwo + col] = red[0][r][c] + red[1][r][c];
+        }
+        return;
+    }
+    const size_t mn = (size_t)g.r1 * g.nc;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
         const int idx = threadIdx.x + 256 * e, r = idx / LR_TN, c = idx % LR_TN;
         const int row = m0 + r, col = n0 + c;
-        if (row < g.r1 && col < g.nc) {
-            const double s = red[0][r][c] + red[1][r][c];
-            if (partials)
-                partials[((size_t)blockIdx.z * g.r1 + row) * g.nc + col] = s;
-            else
-                g.W[(size_t)row * g.ldwo + col] = s;
-        }
+        if (row < g.r1 && col < g.nc)
+            partials[blockIdx.z * mn + (size_t)row * g.nc + col] = red[0][r][c] + red[1][r][c];
     }
 }
 
@@ -142,9 +188,9 @@ int lr_splits(int r0, int n, int r1, int nc) {
     const int64_t K = (int64_t)r0 * n;
     if (K <= 0 || r1 <= 0 || nc <= 0) return 1;
     const int tiles = ceil_div(r1, LR_TM) * ceil_div(nc, LR_TN);
-    // about two workgroups per compute unit, slices of >= 2 chunks
+    // about two workgroups per compute unit, slices of >= 4 chunks
     const int want = std::max(1, ceil_div(512, tiles));
-    const int most = std::max(1, ceil_div(K, 2 * LR_CHUNK));
+    const int most = std::max(1, ceil_div(K, 4 * LR_CHUNK));
     const int s = std::min({want, most, 256});
     return ceil_div(K, lr_kchunk((int)K, s));  // slices actually used
 }
@@ -169,5 +215,6 @@ void launch_lr(const LrArgs& g, int splits, double* partials, hipStream_t s) {
         TTR_CHECK_LAUNCH();
     }
 }
+
 
 }  // namespace ttr
