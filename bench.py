@@ -24,13 +24,14 @@ tensors rounded per second over the timed steps.  Printed beside it, in one JSON
     with events on the launch stream;
   * the partial-contraction kernel at the two sizes where it is a large launch: the
     fixed-rank C2 rounding with an FP32 sketch (HBM-bound) and the adaptive
-    C3 rounding with an FP64 sketch (FP64-MFMA-bound), with their rates;
+    C3 rounding with an FP64 sketch (FP64-MFMA-bound), with their rates,
+    and the left-to-right contractions of C2 (FP64, ell 60);
   * parity of sampled tensors against the CPU oracle and their error
     against X;
   * `cpu_baseline`: the CPU oracle's KRP rounding (and its TT-SVD rounding)
     of a systematic sample of the batch on the host cores, with the thread
     count, and single-threaded.
-Other workloads: --workload c2 | c5 | sum | precision.
+Other workloads: --workload c2 | c5 | sum | precision | lr.
 """
 import argparse
 import json
@@ -142,12 +143,13 @@ def main():
     ap.add_argument("--no-concurrent", action="store_true",
                     help="c2: skip the served-concurrency figure (profiling runs: it would mix "
                          "concurrent kernels into the per-kernel statistics)")
-    ap.add_argument("--workload", choices=["c4", "c2", "c5", "sum", "precision"], default="c4",
+    ap.add_argument("--workload", choices=["c4", "c2", "c5", "sum", "precision", "lr"], default="c4",
                     help="c4 (default): the batch of 256 adaptive roundings at tol 1e-6 (FP64); "
                          "c2: the fixed-rank rounding with an FP32 sketch; c5: served rounding "
                          "under Poisson arrivals (p50/p99 latency); sum: one large C5 request "
                          "rounded term by term vs the assembled formal sum; precision: adaptive "
-                         "rounding of C3 with FP64/FP32/BF16 sketches at tol 1e-4..1e-10")
+                         "rounding of C3 with FP64/FP32/BF16 sketches at tol 1e-4..1e-10; lr: the "
+                         "left-to-right partial contractions of C2 (FP64, ell 60)")
     ap.add_argument("--count", type=int, default=256, help="c4: tensors in the batch")
     ap.add_argument("--plain-reps", type=int, default=3, help="c4: repetitions of the plain loop")
     ap.add_argument("--no-plain", action="store_true",
@@ -181,6 +183,8 @@ def main():
         return run_sum(args)
     if args.workload == "precision":
         return run_precision(args)
+    if args.workload == "lr":
+        return run_lr(args)
     return run_c2(args)
 
 
@@ -218,8 +222,13 @@ def run_headline(args):
     seeds = [42 + t for t in range(len(xs))]
     log("generated and uploaded %d tensors in %.1f s" % (len(xs), time.perf_counter() - t0))
 
-    # the batch laid out once (descriptors uploaded); each step is one
+    # the device's team threshold tuned on this batch (set-up, untimed),
+    # then the batch laid out once (descriptors uploaded); each step is one
     # persistent launch plus the readback of ranks and run records
+    t1 = time.perf_counter()
+    tuned, tune_ms = ttr.batch_autotune(devs, C4_TOL, C4_BLOCK, seeds)
+    tune_s = time.perf_counter() - t1
+    log("autotune: team threshold %.3g (%s) in %.1f s" % (tuned, tune_ms, tune_s))
     t1 = time.perf_counter()
     plan = ttr.BatchPlan(devs, C4_TOL, C4_BLOCK, seeds)
     plan_s = time.perf_counter() - t1
@@ -287,11 +296,15 @@ def run_headline(args):
         "config": {"workload": c4_desc(len(xs)), "tensors": len(xs), "tol": C4_TOL,
                    "ell_block": C4_BLOCK, "sketch_precision": "f64",
                    "input_GB": sum(c.numel() * 8 for x in devs for c in x) / 1e9,
-                   "launch": "one persistent kernel per step (graph-capturable), plan built once"},
+                   "launch": "one persistent kernel per step (graph-capturable), plan built once, "
+                             "team threshold autotuned on the batch beforehand"},
         "step_s": {"median": pctl(step_s, 50), "p10": pctl(step_s, 10), "p90": pctl(step_s, 90),
                    "steps": args.steps},
         "kernel_ms": {"median": pctl(kern_ms, 50), "p10": pctl(kern_ms, 10), "p90": pctl(kern_ms, 90)},
         "plan_create_s": plan_s,
+        "autotune": {"team_flops": tuned, "launch_ms": {"%.0e" % k: v for k, v in tune_ms.items()},
+                     "seconds": tune_s,
+                     "teams": [int(x) for x in np.bincount([plan.team(i) for i in range(len(xs))])]},
         "batch_call_value": len(xs) / pctl(call_s, 50) if call_s else None,
         "plain_value": len(xs) / pctl(plain_s, 50) if plain_s else None,
         "plain_step_s": {"median": pctl(plain_s, 50), "reps": len(plain_s)} if plain_s else None,
@@ -305,7 +318,7 @@ def run_headline(args):
     }
     out["roofline"]["launches_per_step"] = 1
     if not args.no_side:
-        out["side"] = {"c2_f32": side_c2(args), "c3_f64": side_c3(args)}
+        out["side"] = {"c2_f32": side_c2(args), "c3_f64": side_c3(args), "c2_lr_f64": side_lr(args)}
     if not args.no_parity and plain is not None:
         out["parity"] = c4_parity(xs, res, seeds, plain)
     if not args.no_cpu_baseline:
@@ -379,6 +392,53 @@ def side_c3(args):
                                  FP64_MFMA_PEAK_TFLOPS, "partial contraction, FP64 (pc_kernel<double>)"),
             "sketch_GBps": info["pc_bytes"] / (ms / 1e3 / steps) / 1e9, "ranks": info["ranks"],
             "passes": info["passes"]}
+
+
+def lr_model(x, ell):
+    """Algorithmic bytes and flops of one left-to-right pass over every core:
+    each core read once in FP64 and W^L_k (r_k x ell) written; the products
+    2 r_{k-1} n_k r_k ell (the Khatri-Rao operand is formed in registers)."""
+    b = sum(8 * c.shape[0] * c.shape[1] * c.shape[2] + 8 * c.shape[2] * ell for c in x)
+    f = sum(2 * c.shape[0] * c.shape[1] * c.shape[2] * ell for c in x)
+    return b, f
+
+
+def side_lr(args):
+    """The left-to-right partial contractions (Sec. 3.1, the recurrence run
+    from the first core) of C2 with ell = 60 sketch columns in FP64, every
+    core: passes per second and the kernel's roofline."""
+    import torch
+
+    import paper_2511_03598_amd as ttr
+    import ttgen
+
+    x = ttgen.c2(d=D, n=N, r=R)
+    dev = [torch.tensor(c, device="cuda") for c in x]
+    for _ in range(max(1, args.warmup)):
+        ttr.partial_contractions_lr(dev, SEED, 0, ELL)
+    torch.cuda.synchronize()
+    ttr.kernel_timing(True, kinds=["partial_contraction"])
+    times = []
+    for _ in range(args.steps):
+        t1 = time.perf_counter()
+        ttr.partial_contractions_lr(dev, SEED, 0, ELL)
+        times.append(time.perf_counter() - t1)
+    ttr.kernel_timing(False)
+    n, ms = ttr.kernel_timing_read("partial_contraction")
+    per = len(x)  # one timed launch (contraction and slice sum) per core
+    assert n == per * args.steps
+    b, f = lr_model(x, ELL)
+    return {"workload": "left-to-right KRP partial contractions W^L_1..W^L_20 of C2 (d=20, n=64, formal "
+                        "ranks 200), ell=60, FP64", "passes_per_s": 1.0 / pctl(times, 50),
+            "roofline": roofline(b / per, f / per, ms / 1e3 / n, FP64_MFMA_PEAK_TFLOPS,
+                                 "left-to-right contraction, FP64 (lr_kernel and its in-order slice sum)"),
+            "pass_ms_events": ms / args.steps}
+
+
+def run_lr(args):
+    out = side_lr(args)
+    out.update({"steps": args.steps, "warmup": args.warmup})
+    print(json.dumps(out), flush=True)
 
 
 def c4_sample(count, k):

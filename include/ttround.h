@@ -308,6 +308,34 @@ tt_status tt_batch_team(const tt_batch* batch, int32_t i, int32_t* team);
 tt_status tt_batch_record(const tt_batch* batch, int32_t i, double* out, int32_t cap, int32_t* n);
 void tt_batch_destroy(tt_batch* batch);
 
+/* ---- Work-decomposition autotuner of the persistent batch --------------
+ * A tensor of the batch is rounded by a team of T workgroups, T the largest
+ * power of two (at most min(32, resident workgroups / 2)) with 2T times the
+ * device's team threshold F0 below the tensor's work estimate (flops of the
+ * rounding model of Sec. 3.1 and the sweep).  F0 sets how finely the
+ * persistent kernel splits large tensors against how much it pays in team
+ * barriers.  It belongs to the device, not to a batch, so a tensor's team,
+ * and with it the bits of its result, is the same alone or in any batch
+ * created while F0 is unchanged; a batch created before F0 changes keeps
+ * its layout.
+ *
+ * tt_batch_autotune: rounds the given batch (arguments as tt_batch_create,
+ *   results in ys) once per candidate F0 (after one untimed launch), times
+ *   each launch with HIP events on opts->stream into times_ms[j], sets the
+ *   current device's F0 to the fastest candidate (*best) and, when the
+ *   environment variable TTR_BATCH_TUNE_CACHE names a file, appends
+ *   "<gcnArchName>/<compute units> <F0>" to it; the last such line for a
+ *   device is its F0 in later processes.  A set-up call: it allocates and
+ *   frees its own workspace and synchronises the stream.  ncand in [1, 64],
+ *   candidates > 0 (TT_EINVAL otherwise).
+ * tt_batch_team_flops: value > 0 sets the current device's F0, value < 0
+ *   clears it (the cache file, then TTR_BATCH_TEAM_FLOPS, then 3e9 apply),
+ *   0 leaves it; *current (may be NULL) receives the value in force. */
+tt_status tt_batch_autotune(const tt_view* xs, int32_t count, const double* tol, int64_t ell_block,
+                            const uint64_t* seeds, const tt_opts* opts, tt_out* ys, const double* candidates,
+                            int32_t ncand, double* times_ms, double* best);
+tt_status tt_batch_team_flops(double value, double* current);
+
 /* ---- Served rounding ---------------------------------------------------
  * A server owns worker threads (one HIP stream each) on the device current
  * at creation.  Requests queue in arrival order and start as soon as a

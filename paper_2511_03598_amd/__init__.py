@@ -111,6 +111,9 @@ def lib():
             "tt_batch_info": [vp, i32, P(_Info)],
             "tt_batch_team": [vp, i32, P(i32)],
             "tt_batch_record": [vp, i32, P(dbl), i32, P(i32)],
+            "tt_batch_autotune": [P(_View), i32, P(dbl), i64, P(u64), P(_Opts), P(_Out), P(dbl), i32,
+                                  P(dbl), P(dbl)],
+            "tt_batch_team_flops": [dbl, P(dbl)],
             "tt_server_create": [P(_ServerCfg), P(vp)],
             "tt_round_submit": [vp, P(_Request), P(u64)],
             "tt_round_poll": [vp, u64, P(P(_Result))],
@@ -463,6 +466,62 @@ def round_adaptive_batch(tts, tol, ell_block, seeds, f_init=None, nrmx=None, rec
     return res
 
 
+def _batch_arrays(obj, tts, tol, seeds, f_init, nrmx, stream):
+    """Marshal a batch (views, capacity-sized output buffers, tolerances,
+    seeds, options) onto obj."""
+    torch = _torch()
+    obj.count = count = len(tts)
+    tols = [float(tol)] * count if not hasattr(tol, "__len__") else [float(t) for t in tol]
+    sds = [int(seeds)] * count if not hasattr(seeds, "__len__") else [int(x) for x in seeds]
+    obj.tts = tts
+    obj.holders, outs, obj.bufs = [], [], []
+    for cores in tts:
+        h = _ViewHolder(cores)
+        d = len(cores)
+        caps = out_capacity(cores)
+        b = [torch.empty(max(int(c), 1), dtype=torch.float64, device=cores[0].device) for c in caps]
+        rk = (ctypes.c_int64 * (d + 1))()
+        ptrs = (ctypes.c_void_p * d)(*[x.data_ptr() for x in b])
+        capa = (ctypes.c_int64 * d)(*caps)
+        obj.holders.append((h, ptrs, capa, rk))
+        outs.append(_Out(d, rk, ptrs, capa, 0))
+        obj.bufs.append(b)
+    obj.views = (_View * count)(*[h[0].view for h in obj.holders])
+    obj.out_arr = (_Out * count)(*outs)
+    obj.opts = _opts("f64", f_init, nrmx, 0, stream)
+    obj.tol_arr = (ctypes.c_double * count)(*tols)
+    obj.seed_arr = (ctypes.c_uint64 * count)(*sds)
+
+
+BATCH_TUNE_CANDIDATES = (3e8, 1e9, 3e9, 1e10, 1e12)
+
+
+def batch_autotune(tts, tol, ell_block, seeds, candidates=BATCH_TUNE_CANDIDATES, f_init=None, stream=None):
+    """Time the persistent batch once per candidate team threshold and make
+    the fastest the device's (tt_batch_autotune).  Returns (best, {candidate:
+    ms})."""
+    class _A:
+        pass
+    a = _A()
+    _batch_arrays(a, tts, tol, seeds, f_init, None, stream)
+    cands = [float(c) for c in candidates]
+    carr = (ctypes.c_double * len(cands))(*cands)
+    times = (ctypes.c_double * len(cands))()
+    best = ctypes.c_double()
+    _check(lib().tt_batch_autotune(a.views, a.count, a.tol_arr, int(ell_block), a.seed_arr,
+                                   ctypes.byref(a.opts), a.out_arr, carr, len(cands), times,
+                                   ctypes.byref(best)))
+    return float(best.value), {c: float(t) for c, t in zip(cands, times)}
+
+
+def batch_team_flops(value=0.0):
+    """The device's team threshold of the persistent batch: value > 0 sets
+    it, < 0 clears it, 0 only reads it."""
+    cur = ctypes.c_double()
+    _check(lib().tt_batch_team_flops(float(value), ctypes.byref(cur)))
+    return float(cur.value)
+
+
 class BatchPlan:
     """A batch of adaptive roundings laid out for the persistent kernel
     (tt_batch_create): the workspace and the output buffers are torch
@@ -473,27 +532,8 @@ class BatchPlan:
 
     def __init__(self, tts, tol, ell_block, seeds, f_init=None, nrmx=None, stream=None):
         torch = _torch()
-        self.count = count = len(tts)
-        tols = [float(tol)] * count if not hasattr(tol, "__len__") else [float(t) for t in tol]
-        sds = [int(seeds)] * count if not hasattr(seeds, "__len__") else [int(x) for x in seeds]
-        self.tts = tts
-        self.holders, outs, self.bufs = [], [], []
-        for cores in tts:
-            h = _ViewHolder(cores)
-            d = len(cores)
-            caps = out_capacity(cores)
-            b = [torch.empty(max(int(c), 1), dtype=torch.float64, device=cores[0].device) for c in caps]
-            rk = (ctypes.c_int64 * (d + 1))()
-            ptrs = (ctypes.c_void_p * d)(*[x.data_ptr() for x in b])
-            capa = (ctypes.c_int64 * d)(*caps)
-            self.holders.append((h, ptrs, capa, rk))
-            outs.append(_Out(d, rk, ptrs, capa, 0))
-            self.bufs.append(b)
-        self.views = (_View * count)(*[h[0].view for h in self.holders])
-        self.out_arr = (_Out * count)(*outs)
-        self.opts = _opts("f64", f_init, nrmx, 0, stream)
-        self.tol_arr = (ctypes.c_double * count)(*tols)
-        self.seed_arr = (ctypes.c_uint64 * count)(*sds)
+        _batch_arrays(self, tts, tol, seeds, f_init, nrmx, stream)
+        count = self.count
         nbytes = ctypes.c_size_t()
         _check(lib().tt_batch_workspace_bytes(self.views, count, int(ell_block), ctypes.byref(self.opts),
                                               ctypes.byref(nbytes)))

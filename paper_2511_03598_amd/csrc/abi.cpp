@@ -533,6 +533,78 @@ tt_status tt_batch_record(const tt_batch* b, int32_t i, double* out, int32_t cap
 
 void tt_batch_destroy(tt_batch* b) { delete b; }
 
+tt_status tt_batch_autotune(const tt_view* xs, int32_t count, const double* tol, int64_t ell_block,
+                            const uint64_t* seeds, const tt_opts* opts, tt_out* ys, const double* candidates,
+                            int32_t ncand, double* times_ms, double* best) {
+    return guarded([&] {
+        if (!candidates || !times_ms || !best) throw ttr::Error(TT_EINVAL, "null autotune array");
+        if (ncand < 1 || ncand > 64) throw ttr::Error(TT_EINVAL, "ncand must be in [1, 64]");
+        for (int j = 0; j < ncand; ++j)
+            if (!(candidates[j] > 0.0)) throw ttr::Error(TT_EINVAL, "candidates must be > 0");
+        BatchArgs a = batch_args(xs, count, tol, seeds, ys);
+        ttr::Options o = make_opts(opts);
+        const double f_init = o.f_init > 0.0 ? o.f_init : 0.1;
+        hipStream_t st = o.stream;
+        size_t need = 0;
+        for (int j = 0; j < ncand; ++j)
+            need = std::max(need, ttr::batch_workspace_bytes(a.sh, ell_block, f_init, candidates[j]));
+        // tuning is a set-up step: its scratch is allocated here and freed
+        // before returning
+        struct Scratch {
+            void* p = nullptr;
+            hipEvent_t e[2] = {nullptr, nullptr};
+            hipStream_t st = nullptr;
+            ~Scratch() {
+                if (st) (void)hipStreamSynchronize(st);
+                if (p) (void)hipFree(p);
+                for (hipEvent_t x : e)
+                    if (x) (void)hipEventDestroy(x);
+            }
+        } sc;
+        sc.st = st;
+        if (hipMalloc(&sc.p, need) != hipSuccess) {
+            (void)hipGetLastError();
+            sc.p = nullptr;
+            throw ttr::Error(TT_ENOMEM, "autotune workspace allocation of " + std::to_string(need) + " bytes failed");
+        }
+        TTR_HIP(hipEventCreate(&sc.e[0]));
+        TTR_HIP(hipEventCreate(&sc.e[1]));
+        double best_ms = 0.0;
+        int bj = -1;
+        for (int j = 0; j < ncand; ++j) {
+            tt_batch b;
+            TTR_HIP(hipGetDevice(&b.device));
+            b.plan.create(a.sh, a.cores, a.tol, ell_block, a.seeds, o, a.outs, sc.p, need, candidates[j]);
+            b.ys.assign(ys, ys + count);
+            if (j == 0) {  // untimed first launch
+                b.plan.launch(st);
+                batch_finish_impl(&b, st);
+            }
+            TTR_HIP(hipEventRecord(sc.e[0], st));
+            b.plan.launch(st);
+            TTR_HIP(hipEventRecord(sc.e[1], st));
+            batch_finish_impl(&b, st);
+            float ms = 0.f;
+            TTR_HIP(hipEventElapsedTime(&ms, sc.e[0], sc.e[1]));
+            times_ms[j] = ms;
+            if (bj < 0 || ms < best_ms) {
+                best_ms = ms;
+                bj = j;
+            }
+        }
+        *best = candidates[bj];
+        ttr::set_batch_team_flops(*best);
+        ttr::save_batch_team_flops(*best);
+    });
+}
+
+tt_status tt_batch_team_flops(double value, double* current) {
+    return guarded([&] {
+        if (value != 0.0) ttr::set_batch_team_flops(value);
+        if (current) *current = ttr::batch_team_flops();
+    });
+}
+
 tt_status tt_round_adaptive_batch(const tt_view* xs, int32_t count, const double* tol,
                                   int64_t ell_block, const uint64_t* seeds, const tt_opts* opts,
                                   tt_out* ys) {

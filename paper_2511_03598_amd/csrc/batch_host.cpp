@@ -7,6 +7,8 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <fstream>
+#include <mutex>
 #include <numeric>
 
 namespace ttr {
@@ -36,13 +38,79 @@ double tensor_flops(const Shape& s, const std::vector<int64_t>& cap, int64_t lca
 
 }  // namespace
 
-double batch_team_flops() {
-    static const double v = [] {
-        const char* e = std::getenv("TTR_BATCH_TEAM_FLOPS");
-        const double x = e ? std::atof(e) : 0.0;
-        return x > 0.0 ? x : 3.0e9;
-    }();
+namespace {
+std::mutex g_tune_mu;
+constexpr int kTuneDevices = 64;
+double g_tuned[kTuneDevices] = {};
+bool g_cache_read[kTuneDevices] = {};
+
+double env_team_flops() {
+    const char* e = std::getenv("TTR_BATCH_TEAM_FLOPS");
+    const double x = e ? std::atof(e) : 0.0;
+    return x > 0.0 ? x : 3.0e9;
+}
+
+int tune_device() {
+    int dev = 0;
+    TTR_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kTuneDevices) throw Error(-6, "device index out of range");
+    return dev;
+}
+
+// The last entry for `key` in the cache file, or 0.
+double cache_lookup(const std::string& key) {
+    const char* path = std::getenv("TTR_BATCH_TUNE_CACHE");
+    if (!path || !*path) return 0.0;
+    std::ifstream f(path);
+    double v = 0.0;
+    std::string k;
+    double x = 0.0;
+    while (f >> k >> x)
+        if (k == key && x > 0.0) v = x;
     return v;
+}
+}  // namespace
+
+std::string batch_device_key() {
+    int dev = tune_device();
+    hipDeviceProp_t p;
+    TTR_HIP(hipGetDeviceProperties(&p, dev));
+    std::string arch(p.gcnArchName);
+    for (char& c : arch)
+        if (c == ' ') c = '_';
+    return arch + "/" + std::to_string(p.multiProcessorCount);
+}
+
+double batch_team_flops() {
+    const int dev = tune_device();
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        if (g_tuned[dev] > 0.0) return g_tuned[dev];
+        if (g_cache_read[dev]) return env_team_flops();
+    }
+    const double v = cache_lookup(batch_device_key());
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_cache_read[dev] = true;
+    if (v > 0.0 && !(g_tuned[dev] > 0.0)) g_tuned[dev] = v;
+    return g_tuned[dev] > 0.0 ? g_tuned[dev] : env_team_flops();
+}
+
+void set_batch_team_flops(double v) {
+    const int dev = tune_device();
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tuned[dev] = v > 0.0 ? v : 0.0;
+    if (!(v > 0.0)) g_cache_read[dev] = false;
+}
+
+void save_batch_team_flops(double v) {
+    const char* path = std::getenv("TTR_BATCH_TUNE_CACHE");
+    if (!path || !*path || !(v > 0.0)) return;
+    const std::string key = batch_device_key();
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    std::ofstream f(path, std::ios::app);
+    f.precision(17);
+    f << key << " " << v << "\n";
+    if (!f) throw Error(-1, std::string("cannot write the tuning cache ") + path);
 }
 
 // Per-tensor sizes (doubles unless stated) of the workspace regions.
@@ -57,7 +125,7 @@ struct TensorLayout {
     int64_t om = 0, w = 0;
 };
 
-static TensorLayout layout_of(const Shape& s, int64_t ell_block, double f_init, int tmax) {
+static TensorLayout layout_of(const Shape& s, int64_t ell_block, double f_init, int tmax, double f0) {
     TensorLayout L;
     L.s = s;
     const int d = s.d;
@@ -93,7 +161,7 @@ static TensorLayout layout_of(const Shape& s, int64_t ell_block, double f_init, 
     }
     L.flops = tensor_flops(s, L.cap, L.lcap);
     int T = 1;
-    while (T < tmax && (double)(2 * T) * batch_team_flops() <= L.flops) T *= 2;
+    while (T < tmax && (double)(2 * T) * f0 <= L.flops) T *= 2;
     L.T = T;
     L.pslot = std::max<int64_t>(L.lcap * std::max<int64_t>(L.rmax, kBatchMaxBlock), 16);
     L.privs = kBatchPrivRinv + L.lcap * kBatchMaxBlock;
@@ -127,25 +195,28 @@ static size_t header_bytes(int count) {
     return b;
 }
 
-size_t batch_workspace_bytes(const std::vector<Shape>& sh, int64_t ell_block, double f_init) {
+size_t batch_workspace_bytes(const std::vector<Shape>& sh, int64_t ell_block, double f_init, double team_flops) {
     const int tmax = batch_team_cap();
+    const double f0 = team_flops > 0.0 ? team_flops : batch_team_flops();
     size_t b = header_bytes((int)sh.size());
-    for (const Shape& s : sh) b += layout_of(s, ell_block, f_init, tmax).bytes;
+    for (const Shape& s : sh) b += layout_of(s, ell_block, f_init, tmax, f0).bytes;
     return b;
 }
 
 void BatchPlan::create(const std::vector<Shape>& sh, const std::vector<const double* const*>& cores,
                        const std::vector<double>& tol, int64_t ell_block, const std::vector<uint64_t>& seeds,
-                       const Options& o, const std::vector<OutCores>& outs, void* ws, size_t ws_bytes) {
+                       const Options& o, const std::vector<OutCores>& outs, void* ws, size_t ws_bytes,
+                       double team_flops) {
     count = (int)sh.size();
     if (count < 1) throw Error(-1, "a batch needs at least one tensor");
     if (o.prec != 0) throw Error(-6, "batched rounding runs with a float64 sketch only");
     if (o.recompress) throw Error(-6, "batched rounding has no recompression pass");
     const double f_init = (o.f_init > 0.0) ? o.f_init : 0.1;
     const int tmax = batch_team_cap();
+    const double f0 = team_flops > 0.0 ? team_flops : batch_team_flops();
     std::vector<TensorLayout> L;
     L.reserve(count);
-    for (int i = 0; i < count; ++i) L.push_back(layout_of(sh[i], ell_block, f_init, tmax));
+    for (int i = 0; i < count; ++i) L.push_back(layout_of(sh[i], ell_block, f_init, tmax, f0));
     size_t need = header_bytes(count);
     for (const auto& l : L) need += l.bytes;
     if (!ws || ws_bytes < need)

@@ -152,3 +152,45 @@ def test_batch_block_limits(lib):
     with pytest.raises(lib.TTError) as e:
         lib.BatchPlan([to_dev(wide)], 1e-8, 65, [1])
     assert e.value.status == -6
+
+
+def test_batch_autotune_sets_the_device_threshold(lib, tmp_path, monkeypatch):
+    """The autotuner times every candidate team threshold on the batch,
+    makes the fastest the device's and appends it to the cache file; plans
+    created afterwards size their teams by it; a cleared value is read back
+    from the cache file; results under any threshold agree with the plain
+    rounding."""
+    idx, xs = _c4_sample()
+    devs = [to_dev(x) for x in xs]
+    seeds = [42 + t for t in idx]
+    cache = tmp_path / "tune.txt"
+    monkeypatch.setenv("TTR_BATCH_TUNE_CACHE", str(cache))
+    try:
+        best, times = lib.batch_autotune(devs, 1e-6, 16, seeds, candidates=(1e12, 1e8))
+        say("autotune", best, times)
+        assert set(times) == {1e12, 1e8} and all(t > 0 for t in times.values())
+        assert best == min(times, key=times.get)
+        assert lib.batch_team_flops() == best
+        key, val = cache.read_text().split("\n")[-2].split()
+        assert float(val) == best and key.startswith("gfx")
+        # teams follow the device's threshold
+        lib.batch_team_flops(1e12)
+        one = lib.BatchPlan(devs, 1e-6, 16, seeds)
+        assert all(one.team(i) == 1 for i in range(len(xs)))
+        lib.batch_team_flops(1e8)
+        many = lib.BatchPlan(devs, 1e-6, 16, seeds)
+        assert max(many.team(i) for i in range(len(xs))) > 1
+        for plan in (one, many):
+            plan.launch()
+            res = plan.finish()
+            for j in (0, len(xs) - 1):
+                yp, ip = lib.round_adaptive(devs[j], 1e-6, 16, seeds[j])
+                assert res[j][1]["ranks"] == ip["ranks"]
+                assert rel_tensor_diff(xs[j], to_host(res[j][0]), to_host(yp)) <= 1e-12
+        # cleared: the cache file's entry for this device applies again
+        cache.write_text(cache.read_text() + "%s %r\n" % (key, 2.5e9))
+        assert lib.batch_team_flops(-1) == 2.5e9
+    finally:
+        monkeypatch.delenv("TTR_BATCH_TUNE_CACHE")
+        lib.batch_team_flops(-1)  # back to the default for the other tests
+    assert lib.batch_team_flops() == 3e9
