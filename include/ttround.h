@@ -221,13 +221,18 @@ tt_status tt_partial_contractions_lr(const tt_view* x, uint64_t seed, int64_t co
                                      int32_t t, double* const* w, void* stream);
 
 /* Thin QR with diag(R) >= 0 of an m x b column-major float64 device matrix
- * a (ld = m), m >= b >= 1, b <= 64: on return a holds Q (explicit).  The
- * same routine the rounding uses for its sketches. */
+ * a (ld = m), m >= b >= 1, b <= 512: on return a holds Q (explicit).  The
+ * same routine the rounding uses for its sketches: certified CholeskyQR2
+ * with shifted-CholeskyQR3 and Householder fallbacks on panels of at most
+ * 64 columns, and block Gram-Schmidt with reorthogonalisation across
+ * panels when b > 64. */
 tt_status tt_qr(double* a, int64_t m, int64_t b, void* stream);
 
 /* SVD of a small p x q column-major float64 device matrix a (ld = p),
- * p >= q, 1 <= q <= 64, by one-sided Jacobi (the truncated SVD of the
- * right-to-left truncation pass, Remark 2).  Writes g = A V (p x q, ld p,
+ * p >= q, 1 <= q <= 512, by one-sided Jacobi (the truncated SVD of the
+ * right-to-left truncation pass, Remark 2): one workgroup when p, q <= 64,
+ * else one launch per round of the column-pair tournament with a
+ * readback of the rotation count per sweep.  Writes g = A V (p x q, ld p,
  * columns sorted by decreasing norm, i.e. U Sigma), v (q x q, ld q) and
  * sig[q]; *t_out (host) receives the kept rank: the smallest t >= 1 whose
  * tail sqrt(sum_{j>=t} sig_j^2) <= tau when tau >= 0, else

@@ -369,7 +369,7 @@ def partial_contractions_lr(cores, seed, col0, ncols, t=None, stream=None):
 
 
 def svd_small(a, tau=-1.0, target=0, stream=None):
-    """One-sided Jacobi SVD of a (p x q) float64 CUDA tensor, p >= q <= 64.
+    """One-sided Jacobi SVD of a (p x q) float64 CUDA tensor, p >= q <= 512.
     Returns (G = U Sigma sorted, V, sigma, kept rank t)."""
     torch = _torch()
     p, q = a.shape

@@ -166,6 +166,28 @@ void launch_svd_jacobi(const double* A, int lda, int p, int q, double* G, double
                        double* sig, double tau, int target, int* t_out, hipStream_t s,
                        bool trans = false, bool split_only = false);
 
+// Wide one-sided Jacobi (svd.hip), 1 <= q <= p, q <= svd_wide_max(): the
+// same results as launch_svd_jacobi (G = A V sorted by decreasing column
+// norm, Vs, sig, t_out[0] the kept rank, t_out[1] the sweeps) for any
+// width.  The caller drives it: init (Aw = A scaled by a power of two,
+// column-major ld p; Vw = I; sexp one device int), then sweeps of
+// rounds 0 .. Q-2 (Q = q rounded up to even) with *rotated zeroed before
+// each sweep and read after it (0: converged), then finish.  Aw, Vw must
+// not alias A, G or Vs.
+constexpr int kSvdWideMax = 512;
+int svd_wide_max();
+void launch_svd_wide_init(const double* A, int lda, int p, int q, bool trans, double* Aw, double* Vw, int* sexp,
+                          hipStream_t s);
+void launch_svd_wide_round(double* Aw, double* Vw, int p, int q, int round, unsigned* rotated, hipStream_t s);
+void launch_svd_wide_finish(const double* Aw, const double* Vw, const int* sexp, int p, int q, double* G,
+                            double* Vs, double* sig, double tau, int target, int sweeps, int* t_out,
+                            hipStream_t s);
+
+// dst = alpha src + beta dst for a rows x cols strided matrix; src == nullptr
+// reads as zero and beta == 0 does not read dst (so this also fills zeros).
+void launch_axpby2d(const double* src, int64_t ssr, int64_t ssc, double* dst, int64_t dsr, int64_t dsc, int rows,
+                    int cols, double alpha, double beta, hipStream_t s);
+
 int device_lds_limit();
 
 }  // namespace ttr

@@ -85,7 +85,7 @@ struct DevBuf {
 struct Workspace {
     int device = -1;
     DevBuf omega, w, colexp, maxexp, dn, doff, y0, y1, q, sbuf, tbuf, m, qrws, cqws, qrcnt, part, scal,
-        sumpart, sumcnt, small1, small2, small3, small4, tint, tmp, qrsticky;
+        sumpart, sumcnt, small1, small2, small3, small4, tint, tmp, qrsticky, wq1, wq2;
     // Deferred Householder fallback: while a rounding runs with lazy_qr set,
     // qr() launches only the CholeskyQR kernels and a breakdown sets the
     // device int qr_sticky; scalar readbacks fetch it too (host_int[1]) and
@@ -111,7 +111,7 @@ struct Workspace {
         host_int = reinterpret_cast<int*>(host + 32);
         for (DevBuf* b : {&omega, &w, &colexp, &maxexp, &dn, &doff, &y0, &y1, &q, &sbuf, &tbuf, &m, &qrws,
                           &cqws, &qrcnt, &part, &scal, &sumpart, &sumcnt, &small1, &small2, &small3,
-                          &small4, &tint, &tmp, &qrsticky})
+                          &small4, &tint, &tmp, &qrsticky, &wq1, &wq2})
             b->arena = a;
     }
     ~Workspace() {
@@ -287,6 +287,62 @@ void qr(Workspace& ws, hipStream_t s, double* a, int m, int b, int lda, double* 
         std::fprintf(stderr, "ttr qr m=%d b=%d route=%s near_identity_passes=%d\n", m, b,
                      f ? "householder" : (sh ? "shifted-cholqr3" : "cholqr2"), ni);
     }
+}
+
+// Thin QR of any width: block Gram-Schmidt with reorthogonalisation
+// (BCGS2) over panels of at most 64 columns, each panel factored by qr()
+// with its certificate and fallbacks.  R (b x b, column-major, ld b, zero
+// below the diagonal) is written when r_out is given.
+void qr_any(Workspace& ws, hipStream_t s, double* a, int m, int b, int lda, double* r_out = nullptr) {
+    if (b <= 64) {
+        qr(ws, s, a, m, b, lda, r_out);
+        return;
+    }
+    if (m < b) throw Error(-1, "QR needs m >= b");
+    double* C = ws.wq1.as<double>((size_t)b * 64 + 64);  // projection coefficients (p0 x bp, ld p0)
+    double* Rp = ws.wq2.as<double>(64 * 64 + 64);        // R of one panel
+    if (r_out) launch_axpby2d(nullptr, 0, 0, r_out, 1, b, b, b, 0.0, 0.0, s);
+    for (int p0 = 0; p0 < b; p0 += 64) {
+        const int bp = std::min(64, b - p0);
+        double* P = a + (size_t)p0 * lda;
+        for (int pass = 0; pass < (p0 > 0 ? 2 : 0); ++pass) {
+            // C = Q_{<p0}^T P, then P -= Q_{<p0} C, and R[:p0, panel] += C
+            gemm(ws, s, p0, bp, m, a, lda, 1, P, 1, lda, C, 1, p0);
+            gemm(ws, s, m, bp, p0, a, 1, lda, C, 1, p0, P, 1, lda, -1.0, 1.0);
+            if (r_out)
+                launch_axpby2d(C, 1, p0, r_out + (size_t)p0 * b, 1, b, p0, bp, 1.0, pass == 0 ? 0.0 : 1.0, s);
+        }
+        qr(ws, s, P, m, bp, lda, r_out ? Rp : nullptr);
+        if (r_out) launch_copy2d(Rp, 1, bp, r_out + (size_t)p0 * b + p0, 1, b, bp, bp, 1.0, s);
+    }
+}
+
+// Small SVD of any width up to svd_wide_max(): the one-workgroup kernel
+// for p, q <= 64, else the wide Jacobi driven from here (a readback of the
+// rotation count per sweep).  Arguments as launch_svd_jacobi; t_dev holds
+// 16 ints.
+void svd_any(Workspace& ws, hipStream_t st, const double* A, int lda, int p, int q, double* G, double* Vs,
+             double* sig, double tau, int target, int* t_dev, bool trans, bool split_only) {
+    TimedScope ts(KT_SVD, st);
+    if (p <= 64 && q <= 64) {
+        launch_svd_jacobi(A, lda, p, q, G, Vs, sig, tau, target, t_dev, st, trans, split_only);
+        return;
+    }
+    if (q > svd_wide_max() || p < q) throw Error(-6, "SVD wider than 512 columns is not supported");
+    double* Aw = ws.small1.as<double>((size_t)p * q + 64);
+    double* Vw = ws.tmp.as<double>((size_t)q * q + 64);
+    int* sexp = t_dev + 8;
+    unsigned* rot = reinterpret_cast<unsigned*>(t_dev + 9);
+    launch_svd_wide_init(A, lda, p, q, trans, Aw, Vw, sexp, st);
+    const int Q = q + (q & 1);
+    int sweeps = 0;
+    for (int sw = 0; sw < 60 && q >= 2; ++sw) {
+        launch_fill_int(t_dev + 9, 0, 1, st);
+        for (int r = 0; r < Q - 1; ++r) launch_svd_wide_round(Aw, Vw, p, q, r, rot, st);
+        sweeps = sw + 1;
+        if (read_int(ws, st, t_dev + 9) == 0) break;
+    }
+    launch_svd_wide_finish(Aw, Vw, sexp, p, q, G, Vs, sig, tau, target, sweeps, t_dev, st);
 }
 
 double sumsq(Workspace& ws, hipStream_t s, const double* a, int64_t sr, int64_t sc, int rows,
@@ -587,7 +643,7 @@ void recompress(Workspace& ws, hipStream_t st, const Shape& s, double** cores, i
     // every step factors a core whose left rank is an untruncated bond rank:
     // reject before anything of the pass is queued
     for (int k = 1; k < d; ++k)
-        if (ranks[k] > 64) throw Error(-6, "recompression supports ranks <= 64");
+        if (ranks[k] > svd_wide_max()) throw Error(-6, "recompression supports ranks <= 512");
     int64_t maxcore = 0;
     for (int k = 1; k <= d; ++k) maxcore = std::max(maxcore, ranks[k - 1] * s.n[k - 1] * ranks[k]);
     double* buf[2] = {ws.y0.as<double>(maxcore + 64), ws.y1.as<double>(maxcore + 64)};
@@ -608,14 +664,12 @@ void recompress(Workspace& ws, hipStream_t st, const Shape& s, double** cores, i
             // H^T (m x b, column-major) is the row-major H buffer itself; the
             // SVD reads R^T straight from the column-major R.
             double* R = ws.tbuf.as<double>((size_t)b * b + 64);
-            qr(ws, st, H, m, b, m, R);
+            qr_any(ws, st, H, m, b, m, R);
             q = b;
-            TimedScope ts(KT_SVD, st);
-            launch_svd_jacobi(R, b, b, q, G, Vs, sig, tau, tgt, tdev, st, true, tau < 0.0);
+            svd_any(ws, st, R, b, b, q, G, Vs, sig, tau, tgt, tdev, true, tau < 0.0);
         } else {
             q = m;
-            TimedScope ts(KT_SVD, st);
-            launch_svd_jacobi(H, m, b, q, G, Vs, sig, tau, tgt, tdev, st, true, tau < 0.0);
+            svd_any(ws, st, H, m, b, q, G, Vs, sig, tau, tgt, tdev, true, tau < 0.0);
         }
         // a target rank is known on the host; the tail rule needs the device
         const int t = (tau >= 0.0) ? read_int(ws, st, tdev) : std::min(std::max(tgt, 1), q);
@@ -755,6 +809,8 @@ size_t workspace_bytes(const Summands& x, int64_t ell_max, int prec) {
     b += (size_t)lcap * rmax * 8 + (size_t)lcap * 64 * 8;  // M, residual block
     b += 3 * (size_t)maxrows * 64 * 8;                // QR scratch (CholeskyQR + TSQR)
     b += (size_t)64 * 64 * 64 * 8;                    // split-K GEMM partials
+    if (lcap > 64)  // wide QR panels' coefficients, wide SVD (A, V, R, G, Vs)
+        b += ((size_t)lcap * 64 + 5 * (size_t)lcap * lcap + 64 * 64) * 8;
     return b + b / 8 + ((size_t)16 << 20);
 }
 
@@ -810,7 +866,7 @@ static bool round_fixed_once(Workspace& ws, const Summands& x, const int64_t* ta
         const int lk = (int)l[k];
         const Sketch::ZBlocks zb = z_blocks(x, k, ycur);
         sk.sketch_gemm(k, zb, rows, 0, lk, Q, rows);
-        qr(ws, st, Q, rows, lk, rows);
+        qr_any(ws, st, Q, rows, lk, rows);
         project(ws, st, x, zb, k, Q, rows, lk, M);
         launch_copy2d(Q, 1, rows, y.cores[k - 1], lk, 1, rows, lk, 1.0, st);
         double* dst = (k == d - 1) ? y.cores[d - 1] : ybuf[k & 1];
@@ -843,7 +899,7 @@ static bool round_fixed_once(Workspace& ws, const Summands& x, const int64_t* ta
 void round_fixed(const Summands& x, const int64_t* target, int64_t ell, uint64_t seed,
                  const Options& o, OutCores& y, RoundInfo& info) {
     if (ell < 1) throw Error(-1, "ell must be >= 1");
-    if (ell > 64) throw Error(-6, "fixed-rank sketch size ell > 64 is not supported");
+    if (ell > svd_wide_max()) throw Error(-6, "fixed-rank sketch size ell > 512 is not supported");
     WsLease lease(o.stream);
     const bool force = force_qr_retry();
     for (int attempt = 0; attempt < 2; ++attempt) {
@@ -869,7 +925,7 @@ void round_fixed_in(void* region, size_t region_bytes, const Shape& s, const dou
                     const int64_t* target, int64_t ell, uint64_t seed, const Options& o, OutCores& y,
                     RoundInfo& info) {
     if (ell < 1) throw Error(-1, "ell must be >= 1");
-    if (ell > 64) throw Error(-6, "fixed-rank sketch size ell > 64 is not supported");
+    if (ell > svd_wide_max()) throw Error(-6, "fixed-rank sketch size ell > 512 is not supported");
     Arena arena;
     arena.base = static_cast<char*>(region);
     arena.size = region_bytes;
@@ -1134,20 +1190,19 @@ void partial_contractions_lr(const Shape& s, const double* const* cores, uint64_
 void qr_inplace(double* a, int64_t m, int64_t b, hipStream_t st) {
     if (!a || m < 1 || b < 1) throw Error(-1, "bad QR request");
     if (m < b) throw Error(-1, "QR needs m >= b");
+    if (b > svd_wide_max()) throw Error(-6, "QR wider than 512 columns is not supported");
     WsLease lease(st);
-    qr(*lease.ws, st, a, (int)m, (int)b, (int)m);
+    qr_any(*lease.ws, st, a, (int)m, (int)b, (int)m);
     TTR_HIP(hipStreamSynchronize(st));
 }
 
 int64_t svd_small(const double* a, int64_t p, int64_t q, double* g, double* v, double* sig,
                   double tau, int64_t target, hipStream_t st) {
-    if (!a || !g || !v || !sig || q < 1 || q > 64 || p < q) throw Error(-1, "bad SVD request");
+    if (!a || !g || !v || !sig || q < 1 || q > svd_wide_max() || p < q || p > (1 << 20))
+        throw Error(-1, "bad SVD request");
     WsLease lease(st);
     int* tdev = lease->tint.as<int>(16);
-    {
-        TimedScope ts(KT_SVD, st);
-        launch_svd_jacobi(a, (int)p, (int)p, (int)q, g, v, sig, tau, (int)target, tdev, st);
-    }
+    svd_any(*lease.ws, st, a, (int)p, (int)p, (int)q, g, v, sig, tau, (int)target, tdev, false, false);
     return read_int(*lease.ws, st, tdev);
 }
 

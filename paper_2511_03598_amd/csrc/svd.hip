@@ -454,6 +454,193 @@ __global__ void __launch_bounds__(512) svd_jacobi_kernel(const double* A, int ld
     }
 }
 
+// ---------------------------------------------------------------------------
+// Wide one-sided Jacobi (q <= kSvdWideMax columns, p >= q rows).  One
+// workgroup on one CU cannot sweep hundreds of columns quickly: every round
+// moves the whole of A and V through that CU's L2 port.  Here a round of
+// the circle-method tournament (column Q-1 fixed, the others rotating; Q = q
+// rounded up to even, the extra column absent) is one launch with one
+// workgroup per column pair, so a round costs about one launch whatever q
+// is.  A and V are column-major in global memory.  The host runs Q - 1
+// rounds per sweep and reads the sweep's rotation count.
+// ---------------------------------------------------------------------------
+constexpr int kWideThreads = 256;
+
+__device__ __forceinline__ double wide_elem(const double* A, int lda, int trans, int i, int c) {
+    return trans ? A[(size_t)i * lda + c] : A[(size_t)c * lda + i];
+}
+
+// The exponent e of max |A| (2^e > max |A| >= 2^(e-1)): columns are scaled
+// by 2^-e so squared norms neither overflow nor lose small columns.
+__global__ void __launch_bounds__(1024) wide_amax_kernel(const double* A, int lda, int trans, int p, int q,
+                                                         int* sexp) {
+    __shared__ double wmax[16];
+    double m = 0.0;
+    const int64_t total = (int64_t)p * q;
+    for (int64_t t = threadIdx.x; t < total; t += 1024) {
+        const int c = (int)(t / p), i = (int)(t - (int64_t)c * p);
+        m = fmax(m, fabs(wide_elem(A, lda, trans, i, c)));
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off, 64));
+    if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double a = wmax[0];
+        for (int w = 1; w < 16; ++w) a = fmax(a, wmax[w]);
+        int e = 0;
+        if (a > 0.0 && a < INFINITY) (void)frexp(a, &e);
+        sexp[0] = e;
+    }
+}
+
+// Aw = 2^-e A (column-major, ld p), Vw = I (q x q).
+__global__ void __launch_bounds__(256) wide_init_kernel(const double* A, int lda, int trans, int p, int q,
+                                                        const int* sexp, double* Aw, double* Vw) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t na = (int64_t)p * q, nv = (int64_t)q * q;
+    const int e = sexp[0];
+    if (t < na) {
+        const int c = (int)(t / p), i = (int)(t - (int64_t)c * p);
+        Aw[t] = ldexp(wide_elem(A, lda, trans, i, c), -e);
+    } else if (t < na + nv) {
+        const int64_t u = t - na;
+        const int c = (int)(u / q), i = (int)(u - (int64_t)c * q);
+        Vw[u] = (i == c) ? 1.0 : 0.0;
+    }
+}
+
+// Pair blockIdx.x of round r: (r, Q-1) for the first pair, else the columns
+// (r + k) and (r - k) modulo Q - 1.  Each thread sums its rows of the three
+// inner products; the waves' partials are added in wave order.
+__global__ void __launch_bounds__(kWideThreads) wide_round_kernel(double* Aw, double* Vw, int p, int q, int Q,
+                                                                  int r, double tol2, unsigned* rotated) {
+    __shared__ double part[3][kWideThreads / 64];
+    const int k = blockIdx.x, m = Q - 1;
+    int i, j;
+    if (k == 0) {
+        i = r;
+        j = m;
+    } else {
+        i = (r + k) % m;
+        j = (r - k + m) % m;
+    }
+    if (i >= q || j >= q) return;  // the absent column of an odd q (uniform per workgroup)
+    double* x = Aw + (size_t)i * p;
+    double* y = Aw + (size_t)j * p;
+    double al = 0.0, be = 0.0, ga = 0.0;
+    for (int t = threadIdx.x; t < p; t += kWideThreads) {
+        const double a = x[t], b = y[t];
+        al = fma(a, a, al);
+        be = fma(b, b, be);
+        ga = fma(a, b, ga);
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        al += __shfl_xor(al, off, 64);
+        be += __shfl_xor(be, off, 64);
+        ga += __shfl_xor(ga, off, 64);
+    }
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        part[0][w] = al;
+        part[1][w] = be;
+        part[2][w] = ga;
+    }
+    __syncthreads();
+    al = part[0][0];
+    be = part[1][0];
+    ga = part[2][0];
+#pragma unroll
+    for (int u = 1; u < kWideThreads / 64; ++u) {
+        al += part[0][u];
+        be += part[1][u];
+        ga += part[2][u];
+    }
+    if (!(ga * ga > tol2 * (al * be))) return;  // uniform: already orthogonal to the tolerance
+    if (threadIdx.x == 0) atomicAdd(rotated, 1u);
+    double c, sn;
+    jacobi_cs(al, be, ga, c, sn);
+    for (int t = threadIdx.x; t < p; t += kWideThreads) {
+        const double a = x[t], b = y[t];
+        x[t] = c * a - sn * b;
+        y[t] = sn * a + c * b;
+    }
+    double* vx = Vw + (size_t)i * q;
+    double* vy = Vw + (size_t)j * q;
+    for (int t = threadIdx.x; t < q; t += kWideThreads) {
+        const double a = vx[t], b = vy[t];
+        vx[t] = c * a - sn * b;
+        vy[t] = sn * a + c * b;
+    }
+}
+
+// Column norms, order by decreasing norm (ties by index), G = A V sorted and
+// rescaled, Vs, sig and the kept rank by the tail rule (tau >= 0) or the
+// target, as the one-workgroup kernel reports them.
+__global__ void __launch_bounds__(1024) wide_finish_kernel(const double* Aw, const double* Vw, const int* sexp,
+                                                           int p, int q, double* G, double* Vs, double* sig,
+                                                           double tau, int target, int sweeps, int* t_out) {
+    __shared__ double nd[kSvdWideMax], sg[kSvdWideMax];
+    __shared__ int perm[kSvdWideMax];
+    const int e = sexp[0];
+    for (int c = threadIdx.x; c < q; c += 1024) {
+        const double* col = Aw + (size_t)c * p;
+        double s = 0.0;
+        for (int i = 0; i < p; ++i) s = fma(col[i], col[i], s);
+        nd[c] = s;
+        sg[c] = ldexp(sqrt(s), e);
+        perm[c] = c;  // a valid column in every slot even if a NaN norm breaks the ranking
+    }
+    __syncthreads();
+    int rank_of[(kSvdWideMax + 1023) / 1024];
+#pragma unroll
+    for (int u = 0; u < (kSvdWideMax + 1023) / 1024; ++u) {
+        const int c = threadIdx.x + 1024 * u;
+        int cnt = -1;
+        if (c < q) {
+            const double me = nd[c];
+            cnt = 0;
+            for (int o = 0; o < q; ++o) cnt += (nd[o] > me) || (nd[o] == me && o < c);
+        }
+        rank_of[u] = cnt;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < (kSvdWideMax + 1023) / 1024; ++u)
+        if (rank_of[u] >= 0 && rank_of[u] < q) perm[rank_of[u]] = threadIdx.x + 1024 * u;
+    __syncthreads();
+    for (int64_t t = threadIdx.x; t < (int64_t)p * q; t += 1024) {
+        const int rr = (int)(t / p), i = (int)(t - (int64_t)rr * p);
+        G[t] = ldexp(Aw[(size_t)perm[rr] * p + i], e);
+    }
+    for (int64_t t = threadIdx.x; t < (int64_t)q * q; t += 1024) {
+        const int rr = (int)(t / q), i = (int)(t - (int64_t)rr * q);
+        Vs[t] = Vw[(size_t)perm[rr] * q + i];
+    }
+    for (int c = threadIdx.x; c < q; c += 1024) sig[c] = sg[perm[c]];
+    if (threadIdx.x == 0) {
+        int t = q;
+        if (tau >= 0.0) {
+            double acc = 0.0;
+            for (int rr = q - 1; rr >= 1; --rr) {
+                const double sv = sg[perm[rr]];
+                acc += sv * sv;
+                if (sqrt(acc) <= tau)
+                    t = rr;
+                else
+                    break;
+            }
+        } else {
+            t = min(max(target, 1), q);
+        }
+        t_out[0] = t;
+        t_out[1] = sweeps;
+        t_out[2] = 0;
+        t_out[3] = 0;
+    }
+}
+
 }  // namespace
 
 void launch_svd_jacobi(const double* A, int lda, int p, int q, double* G, double* Vs, double* sig,
@@ -463,6 +650,43 @@ void launch_svd_jacobi(const double* A, int lda, int p, int q, double* G, double
         throw Error(-6, "small SVD: need 1 <= q <= p <= 64");
     hipLaunchKernelGGL(svd_jacobi_kernel, dim3(1), dim3(512), 0, s, A, lda, trans ? 1 : 0, p, q, G, Vs, sig,
                        tau, target, t_out, split_only ? 1 : 0);
+    TTR_CHECK_LAUNCH();
+}
+
+int svd_wide_max() { return kSvdWideMax; }
+
+double svd_wide_tol2(int p) {
+    // rotate while (x.y)^2 > tol^2 (x.x)(y.y), tol well above the rounding
+    // error of a p-term inner product so that a sweep can end without one
+    const double tol = 1e-13 * std::max(1.0, (double)p / 64.0);
+    return tol * tol;
+}
+
+void launch_svd_wide_init(const double* A, int lda, int p, int q, bool trans, double* Aw, double* Vw, int* sexp,
+                          hipStream_t s) {
+    if (q < 1 || q > kSvdWideMax || p < q) throw Error(-6, "wide SVD: need 1 <= q <= p, q <= 512");
+    hipLaunchKernelGGL(wide_amax_kernel, dim3(1), dim3(1024), 0, s, A, lda, trans ? 1 : 0, p, q, sexp);
+    TTR_CHECK_LAUNCH();
+    const int64_t work = (int64_t)p * q + (int64_t)q * q;
+    hipLaunchKernelGGL(wide_init_kernel, dim3(ceil_div(work, 256)), dim3(256), 0, s, A, lda, trans ? 1 : 0, p, q,
+                       sexp, Aw, Vw);
+    TTR_CHECK_LAUNCH();
+}
+
+void launch_svd_wide_round(double* Aw, double* Vw, int p, int q, int round, unsigned* rotated, hipStream_t s) {
+    const int Q = q + (q & 1);
+    if (Q < 2 || round < 0 || round >= Q - 1) throw Error(-1, "wide SVD: bad round");
+    hipLaunchKernelGGL(wide_round_kernel, dim3(Q / 2), dim3(kWideThreads), 0, s, Aw, Vw, p, q, Q, round,
+                       svd_wide_tol2(p), rotated);
+    TTR_CHECK_LAUNCH();
+}
+
+void launch_svd_wide_finish(const double* Aw, const double* Vw, const int* sexp, int p, int q, double* G,
+                            double* Vs, double* sig, double tau, int target, int sweeps, int* t_out,
+                            hipStream_t s) {
+    if (q < 1 || q > kSvdWideMax || p < q) throw Error(-6, "wide SVD: need 1 <= q <= p, q <= 512");
+    hipLaunchKernelGGL(wide_finish_kernel, dim3(1), dim3(1024), 0, s, Aw, Vw, sexp, p, q, G, Vs, sig, tau, target,
+                       sweeps, t_out);
     TTR_CHECK_LAUNCH();
 }
 

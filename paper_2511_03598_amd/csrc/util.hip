@@ -25,6 +25,25 @@ __global__ void __launch_bounds__(256) copy2d_kernel(const double* __restrict__ 
     dst[(size_t)r * dsr + (size_t)c * dsc] = scale * src[(size_t)r * ssr + (size_t)c * ssc];
 }
 
+__global__ void __launch_bounds__(256) axpby2d_kernel(const double* __restrict__ src, int64_t ssr, int64_t ssc,
+                                                      double* __restrict__ dst, int64_t dsr, int64_t dsc, int rows,
+                                                      int cols, double alpha, double beta) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)rows * cols) return;
+    int r, c;
+    if (dsc == 1) {
+        r = (int)(t / cols);
+        c = (int)(t - (int64_t)r * cols);
+    } else {
+        c = (int)(t / rows);
+        r = (int)(t - (int64_t)c * rows);
+    }
+    double* d = dst + (size_t)r * dsr + (size_t)c * dsc;
+    double v = src ? alpha * src[(size_t)r * ssr + (size_t)c * ssc] : 0.0;
+    if (beta != 0.0) v += beta * (*d);
+    *d = v;
+}
+
 constexpr int kSumBlocks = 1024;
 
 __global__ void __launch_bounds__(256) sumsq_kernel(const double* __restrict__ a, int64_t sr,
@@ -84,6 +103,15 @@ void launch_copy2d(const double* src, int64_t ssr, int64_t ssc, double* dst, int
     if (work <= 0) return;
     hipLaunchKernelGGL(copy2d_kernel, dim3(ceil_div(work, 256)), dim3(256), 0, s, src, ssr, ssc,
                        dst, dsr, dsc, rows, cols, scale);
+    TTR_CHECK_LAUNCH();
+}
+
+void launch_axpby2d(const double* src, int64_t ssr, int64_t ssc, double* dst, int64_t dsr, int64_t dsc, int rows,
+                    int cols, double alpha, double beta, hipStream_t s) {
+    const int64_t work = (int64_t)rows * cols;
+    if (work <= 0) return;
+    hipLaunchKernelGGL(axpby2d_kernel, dim3(ceil_div(work, 256)), dim3(256), 0, s, src, ssr, ssc, dst, dsr, dsc,
+                       rows, cols, alpha, beta);
     TTR_CHECK_LAUNCH();
 }
 

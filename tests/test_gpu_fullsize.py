@@ -12,7 +12,9 @@ Gaussian factors:
     assembled formal sum and sketched term by term -- ranks near 380,
     regeneration with capacity doubling, split-K projections over K ~ 12k;
   * eight C4 tensors (including the largest d n r of the 256), rounded by
-    the batch entry point.
+    the batch entry point;
+  * C3 and the large C5 request with the Remark 2 truncation pass after the
+    adaptive sweep (bond ranks 74-94 and near 380 reach the pass).
 
 Bar: ||Y_gpu - Y_oracle|| / ||X|| <= 1e-10 (FP64 sketch) or 1e-5 (FP32
 sketch) with equal ranks.  ||X|| is replaced by ||Y_oracle|| (cheap for the
@@ -96,6 +98,36 @@ def test_sum_adaptive_c5_large_request_terms(lib, c5_large):
     yg, ig = lib.round_sum_adaptive([to_dev(t) for t in tts], 1e-6, 20, 7, weights=coef)
     x = ttgen.formal_sum(tts, coef)
     _compare(x, to_host(yg), ig, yo, io, "f64", 1e-6)
+
+
+def test_adaptive_recompress_c3_full_size(lib, c3, c3_oracle):
+    """Adaptive rounding of C3 at tol 1e-6 followed by the Remark 2
+    right-to-left truncation pass (the paper's Adap-R): the bonds reach the
+    pass at ranks 74-94, so every step runs the panel-blocked QR and the
+    wide Jacobi SVD.  Oracle: its truncation pass applied to its own
+    adaptive result with the same tau."""
+    yo0, io = c3_oracle
+    yo = krp.recompress_rl(yo0, tau=io["tau"])
+    io = dict(io, ranks=[1] + [c.shape[2] for c in yo])
+    say("adaptive + recompression C3 full size; oracle ranks", io["ranks"])
+    assert max(c.shape[2] for c in yo0) > 64
+    yg, ig = lib.round_adaptive(to_dev(c3), 1e-6, 16, 42, recompress=1)
+    _compare(c3, to_host(yg), ig, yo, io, "f64", 2e-6)
+    assert tt.right_orth_defect(to_host(yg)) < 1e-12
+
+
+def test_adaptive_recompress_c5_large_request(lib, c5_large):
+    """Adap-R on the large C5 request (formal sum, bond ranks near 380 before
+    the truncation pass: wide QRs of 12k-row panels and 380-column Jacobi
+    SVDs)."""
+    tts, coef, yo0, io = c5_large
+    yo = krp.recompress_rl(yo0, tau=io["tau"])
+    io = dict(io, ranks=[1] + [c.shape[2] for c in yo])
+    x = ttgen.formal_sum(tts, coef)
+    say("adaptive + recompression C5 large request; oracle ranks", io["ranks"])
+    yg, ig = lib.round_adaptive(to_dev(x), 1e-6, 20, 7, recompress=1)
+    assert max(c.shape[2] for c in yo0) > 300
+    _compare(x, to_host(yg), ig, yo, io, "f64", 2e-6)
 
 
 def _c4_sample():

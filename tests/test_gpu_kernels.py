@@ -270,6 +270,42 @@ def test_svd_small_matches_lapack(lib, p, q):
     assert t2 == min(5, q)
 
 
+@pytest.mark.parametrize("m,b", [(300, 100), (3000, 200), (129, 129), (20000, 80), (600, 512)])
+def test_qr_wide_matches_householder(lib, m, b):
+    """Panels past 64 columns: block Gram-Schmidt with reorthogonalisation
+    over 64-column panels, each factored by the certified CholeskyQR."""
+    import torch
+    say("qr wide", m, b)
+    rng = np.random.default_rng(m + 7 * b)
+    a = rng.standard_normal((m, b)) * (10.0 ** (-np.arange(b) / 64.0))[None, :]
+    q = lib.qr(torch.tensor(a, device="cuda")).cpu().numpy()
+    ref = krp.qr_pos(a)
+    assert np.max(np.abs(q.T @ q - np.eye(b))) < 1e-13
+    assert np.max(np.abs(q - ref)) < 1e-10
+
+
+@pytest.mark.parametrize("p,q", [(100, 100), (200, 130), (65, 65), (380, 380), (512, 512), (300, 40)])
+def test_svd_wide_matches_lapack(lib, p, q):
+    """The many-workgroup Jacobi (one launch per round of the tournament)
+    for widths past 64 or heights past 64: singular values to high relative
+    accuracy on graded columns, A V = G, orthonormal V, the tail rule."""
+    import torch
+    from oracle.ttsvd import truncation_rank
+    say("svd wide", p, q)
+    rng = np.random.default_rng(p * 13 + q)
+    a = rng.standard_normal((p, q)) * (10.0 ** (-np.arange(q) / 40.0))[None, :]
+    g, v, sig, t = lib.svd_small(torch.tensor(a, device="cuda"), tau=1e-3)
+    g, v, sig = g.cpu().numpy(), v.cpu().numpy(), sig.cpu().numpy()
+    s_ref = np.linalg.svd(a, compute_uv=False)
+    assert np.max(np.abs(sig - s_ref) / s_ref) < 1e-11
+    assert np.all(np.diff(sig) <= 0)
+    assert np.max(np.abs(v.T @ v - np.eye(q))) < 1e-12
+    assert np.linalg.norm(a @ v - g) < 1e-12 * np.linalg.norm(a)
+    assert t == truncation_rank(s_ref, 1e-3)
+    _, _, _, t2 = lib.svd_small(torch.tensor(a, device="cuda"), tau=-1.0, target=70)
+    assert t2 == min(70, q)
+
+
 def test_svd_small_rank_deficient(lib):
     import torch
     rng = np.random.default_rng(4)

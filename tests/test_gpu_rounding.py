@@ -105,6 +105,40 @@ def test_fixed_c2_full_size(lib, prec):
     _check_orth(yg, ig)
 
 
+@pytest.mark.parametrize("target", [None, 60])
+def test_fixed_wide_sketch_sec41(lib, target):
+    """ell = 80, the widest sketch of the paper's Sec. 4.1 sweep, on its
+    recipe X = Y + 1e-5 Z (d=10, n=100, ranks 50 + 50): 80-column sketch
+    QRs (two panels, block Gram-Schmidt) and, with target ranks 60, the
+    80 -> 60 truncations by the wide Jacobi SVD."""
+    say("fixed Sec. 4.1 recipe, ell 80, target", target)
+    x = ttgen.sec41()
+    tgt = None if target is None else [1] + [target] * (len(x) - 1) + [1]
+    yg, ig = _fixed(lib, x, 80, 11, tgt)
+    yo, io = krp.round_fixed(x, 80, 11, tgt)
+    assert ig["ranks"] == io["ranks"]
+    assert max(ig["ranks"]) == (80 if target is None else 60)
+    d = rel_tensor_diff(x, yg, yo)
+    say("  rel diff vs oracle", d)
+    assert d <= TOL["f64"]
+    _check_orth(yg, ig)
+
+
+def test_adaptive_recompress_ranks_above_64(lib):
+    """Adaptive rounding plus the Remark 2 pass on a tensor whose bond ranks
+    exceed 64 (orthonormal cores, slowly decaying spectra)."""
+    x = ttgen.c3(seed=7, d=4, n=16, r=100, noise_r=10, decay=40.0)
+    yg, ig = lib.round_adaptive(to_dev(x), 1e-6, 16, 3, recompress=1)
+    yo, io = krp.round_adaptive(x, 1e-6, 16, 3, recompress=1)
+    say("adaptive + recompression, ranks", ig["ranks"], io["ranks"])
+    assert max(io["ranks"]) > 64
+    yg = to_host(yg)
+    assert _ranks_equal_or_tie(ig, io, ig["ranks"], io["ranks"], x, (yg, yo), 2e-6)
+    if ig["ranks"] == io["ranks"]:
+        assert rel_tensor_diff(x, yg, yo) <= TOL["f64"]
+    assert tt.right_orth_defect(yg) < 1e-12
+
+
 @pytest.mark.parametrize("seed", [31, 32])
 def test_fixed_truncation_without_spectral_gap(lib, seed):
     """Truncating a random TT (no gap in its bond spectra) from ell = 24 to

@@ -149,14 +149,15 @@ def test_server_poll_until_done(lib):
 
 def test_server_failed_request_leaves_neighbours_intact(lib):
     """A request that the library rejects after its sweep has been queued
-    (Remark 2 recompression of ranks above the truncation kernel's limit)
+    (Remark 2 recompression of ranks above the truncation pass's limit of
+    512, on a flat bond spectrum)
     returns TT_EUNSUPPORTED, and the requests served beside it stay bitwise
     equal to their solo runs (the failed request's buffers go back to the
     pools only after its stream has drained)."""
-    wide = ttgen.c3(seed=7, d=4, n=16, r=100, noise_r=10, decay=40.0)
+    wide = ttgen.c3(seed=7, d=4, n=32, r=600, noise_r=10, decay=1e9)
     dw = to_dev(wide)
     y_alone, i_alone = lib.round_adaptive(dw, 1e-6, 16, 3)
-    assert max(i_alone["ranks"]) > 64
+    assert max(i_alone["ranks"]) > 512
     xs = _mix(6, 600)
     devs = [to_dev(x) for x in xs]
     solo = [lib.round_adaptive(dv, 1e-6, 4, 20 + i) for i, dv in enumerate(devs)]
