@@ -179,6 +179,22 @@ tt_status tt_round_sum_adaptive(const tt_view* xs, int32_t count, const double* 
                                 double tol, int64_t ell_block, uint64_t seed, const tt_opts* opts,
                                 tt_out* y);
 
+/* Deterministic TT-SVD rounding (Sec. 2.3, Algorithm "TT-Rounding"), the
+ * same-GPU baseline of the randomized roundings: right-to-left
+ * orthogonalisation of a working copy of x, then tau = tol ||X|| /
+ * sqrt(d-1) and, left to right, a thin QR of V(Y_k), the SVD of its R
+ * truncated by the tail rule (smallest t with sqrt(sum_{j>=t} s_j^2) <=
+ * tau), Y_k = Q U_t and Y_{k+1} = S_t V_t^T H(Y_{k+1}).  With
+ * target_ranks (host [d+1], interior entries >= 1) the bonds are truncated
+ * to min(target, available) instead and tol is ignored.  Output: y
+ * (capacities from tt_out_capacity), left-orthonormal (orth = 1); the
+ * input is not modified.  Interior ranks up to 512 (TT_EUNSUPPORTED
+ * otherwise).  Uses the library's workspace (about the size of x plus a
+ * few cores), synchronises opts->stream, and records tau and ||X|| for
+ * tt_last_info. */
+tt_status tt_round_ttsvd(const tt_view* x, double tol, const int64_t* target_ranks, const tt_opts* opts,
+                         tt_out* y);
+
 /* Diagnostics of the calling thread's last tt_round_* call. */
 tt_status tt_last_info(tt_info* info);
 

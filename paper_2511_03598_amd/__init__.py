@@ -93,6 +93,7 @@ def lib():
             "tt_round_fixed": [P(_View), P(i64), i64, u64, P(_Opts), P(_Out)],
             "tt_round_fixed_noalloc": [P(_View), P(i64), i64, u64, P(_Opts), P(_Out)],
             "tt_round_adaptive": [P(_View), dbl, i64, u64, P(_Opts), P(_Out)],
+            "tt_round_ttsvd": [P(_View), dbl, P(i64), P(_Opts), P(_Out)],
             "tt_last_info": [P(_Info)],
             "tt_gaussian_factor": [u64, i32, i64, i64, i64, vp, vp],
             "tt_philox4x32_10": [vp, vp, vp, i64, vp],
@@ -246,6 +247,17 @@ def round_adaptive(cores, tol, ell_block, seed, nrmx=None, f_init=None, recompre
     return _run(cores, lambda h, out: lib().tt_round_adaptive(
         ctypes.byref(h.view), float(tol), int(ell_block), ctypes.c_uint64(seed),
         ctypes.byref(o), ctypes.byref(out)))
+
+
+def round_ttsvd(cores, tol=None, target_ranks=None, stream=None):
+    """Deterministic TT-SVD rounding (Sec. 2.3) to relative tolerance tol,
+    or to target_ranks (d+1 list).  Returns (cores, info)."""
+    if (tol is None) == (target_ranks is None):
+        raise ValueError("give exactly one of tol or target_ranks")
+    o = _opts("f64", None, None, 0, stream)
+    tg = None if target_ranks is None else (ctypes.c_int64 * len(target_ranks))(*[int(t) for t in target_ranks])
+    return _run(cores, lambda h, out: lib().tt_round_ttsvd(
+        ctypes.byref(h.view), float(tol or 0.0), tg, ctypes.byref(o), ctypes.byref(out)))
 
 
 class _SumHolder:

@@ -300,6 +300,23 @@ tt_status tt_round_adaptive(const tt_view* x, double tol, int64_t ell_block, uin
     });
 }
 
+tt_status tt_round_ttsvd(const tt_view* x, double tol, const int64_t* target_ranks, const tt_opts* opts,
+                         tt_out* y) {
+    return guarded([&] {
+        ttr::Shape s = view_shape(x);
+        ttr::Options o = make_opts(opts);
+        if (!target_ranks && !(tol > 0.0)) throw ttr::Error(TT_EINVAL, "tol must be > 0");
+        if (target_ranks)
+            for (int k = 1; k < s.d; ++k)
+                if (target_ranks[k] < 1) throw ttr::Error(TT_EINVAL, "target ranks must be >= 1");
+        ttr::OutCores oc = out_of(y, s.d);
+        ttr::RoundInfo info;
+        ttr::round_ttsvd(s, x->cores, tol, target_ranks, o, oc, info);
+        y->orth = oc.orth;
+        store_info(info);
+    });
+}
+
 tt_status tt_last_info(tt_info* info) {
     if (!info) return fail(TT_EINVAL, "null info");
     *info = g_info;

@@ -1089,6 +1089,115 @@ void round_adaptive(const Shape& s, const double* const* cores, double tol, int6
 }
 
 // ---------------------------------------------------------------------------
+// Deterministic TT-SVD rounding (Sec. 2.3, Algorithm "TT-Rounding"): the
+// same-GPU baseline of the randomized roundings.
+// ---------------------------------------------------------------------------
+// Right-to-left orthogonalisation of a working copy of X, then tau =
+// tol ||Y_1|| / sqrt(d-1), then left to right: V(Y_k) = Q R, the SVD of R
+// truncated by the tail rule (or to the target rank), Y_k = Q U_t,
+// Y_{k+1} = S_t V_t^T H(Y_{k+1}).  The Jacobi runs on R^T (R^T W = G with
+// orthogonal W), so U_t = W_t and S_t V_t^T = G_t^T come out without a
+// division by a singular value.  A factor with fewer rows than columns is
+// taken by the SVD alone (its QR would not be thin).
+void round_ttsvd(const Shape& s, const double* const* cores, double tol, const int64_t* target,
+                 const Options& o, OutCores& y, RoundInfo& info) {
+    const int d = s.d;
+    hipStream_t st = o.stream;
+    if (!target && !(tol > 0.0)) throw Error(-1, "tol must be > 0");
+    for (int k = 1; k < d; ++k)
+        if (s.r[k] > svd_wide_max()) throw Error(-6, "TT-SVD supports ranks <= 512");
+    WsLease lease(st);
+    Workspace& ws = *lease.ws;
+    std::vector<int64_t> off(d + 1, 0), r(s.r);
+    int64_t maxcore = 1;
+    for (int k = 1; k <= d; ++k) {
+        const int64_t sz = s.r[k - 1] * s.n[k - 1] * s.r[k];
+        off[k] = off[k - 1] + sz;
+        maxcore = std::max(maxcore, sz);
+    }
+    double* Z = ws.w.as<double>(off[d] + 64);  // working copy of the cores
+    for (int k = 1; k <= d; ++k)
+        TTR_HIP(hipMemcpyAsync(Z + off[k - 1], cores[k - 1], (size_t)(off[k] - off[k - 1]) * sizeof(double),
+                               hipMemcpyDeviceToDevice, st));
+    double* tmp = ws.y0.as<double>(maxcore + 64);
+    int rmax = 1;
+    for (int k = 0; k <= d; ++k) rmax = std::max<int>(rmax, (int)s.r[k]);
+    double* R = ws.tbuf.as<double>((size_t)rmax * rmax + 64);
+    double* G = ws.small2.as<double>((size_t)rmax * rmax + 64);
+    double* Vs = ws.small3.as<double>((size_t)rmax * rmax + 64);
+    double* sig = ws.small4.as<double>(rmax + 64);
+    int* tdev = ws.tint.as<int>(16);
+
+    // 1. right-to-left orthogonalisation (ranks only shrink)
+    for (int k = d; k >= 2; --k) {
+        const int b = (int)r[k - 1];
+        const int m = (int)(s.n[k - 1] * r[k]);
+        double* H = Z + off[k - 1];  // H(Y_k): b x m row-major = H^T column-major (ld m)
+        double* Yp = Z + off[k - 2];
+        const int rows = (int)(r[k - 2] * s.n[k - 2]);
+        if (m >= b) {
+            qr_any(ws, st, H, m, b, m, R);  // H^T = Q R: the new H(Y_k) is Q^T in place
+            gemm(ws, st, rows, b, b, Yp, b, 1, R, b, 1, tmp, b, 1);  // V(Y_{k-1}) R^T
+            TTR_HIP(hipMemcpyAsync(Yp, tmp, (size_t)rows * b * sizeof(double), hipMemcpyDeviceToDevice, st));
+        } else {
+            // H (b x m, b > m) = G W^T: the new H(Y_k) is W^T (m x m), V(Y_{k-1}) G
+            svd_any(ws, st, H, m, b, m, G, Vs, sig, -1.0, m, tdev, true, false);
+            TTR_HIP(hipMemcpyAsync(H, Vs, (size_t)m * m * sizeof(double), hipMemcpyDeviceToDevice, st));
+            gemm(ws, st, rows, m, b, Yp, b, 1, G, 1, b, tmp, m, 1);
+            TTR_HIP(hipMemcpyAsync(Yp, tmp, (size_t)rows * m * sizeof(double), hipMemcpyDeviceToDevice, st));
+            r[k - 1] = m;
+        }
+    }
+    // 2. the bond threshold from ||Y_1||
+    const double nrm = std::sqrt(sumsq(ws, st, Z, (int64_t)1, 0, (int)(r[0] * s.n[0] * r[1]), 1));
+    const double tau = target ? -1.0 : tol * nrm / std::sqrt((double)(d - 1));
+    info = RoundInfo{};
+    info.tau = tau;
+    info.nrmx = nrm;
+    // 3. left-to-right truncation
+    double* cur = Z;  // V(Y_k), row-major rows x b
+    double* carry[2] = {ws.y1.as<double>(maxcore + 64), tmp};
+    double* T = ws.q.as<double>(maxcore + 64);
+    for (int k = 1; k < d; ++k) {
+        const int b = (int)r[k];
+        const int rows = (int)(r[k - 1] * s.n[k - 1]);
+        const int tgt = target ? (int)target[k] : 0;
+        int q;
+        if (rows >= b) {
+            launch_copy2d(cur, b, 1, T, 1, rows, rows, b, 1.0, st);  // to column-major
+            qr_any(ws, st, T, rows, b, rows, R);
+            q = b;
+            svd_any(ws, st, R, b, b, q, G, Vs, sig, tau, tgt, tdev, true, false);
+        } else {
+            q = rows;  // V(Y_k)^T (b x rows) is the row-major buffer read column-major
+            svd_any(ws, st, cur, b, b, q, G, Vs, sig, tau, tgt, tdev, false, false);
+        }
+        const int t = (tau >= 0.0) ? read_int(ws, st, tdev) : std::min(std::max(tgt, 1), q);
+        if ((int64_t)rows * t > y.cap[k - 1])
+            throw Error(-2, "output core " + std::to_string(k) + " needs " + std::to_string((int64_t)rows * t) +
+                                " elements, capacity " + std::to_string(y.cap[k - 1]));
+        if (rows >= b)
+            gemm(ws, st, rows, t, b, T, 1, rows, Vs, 1, q, y.cores[k - 1], t, 1);  // Q W_t
+        else
+            launch_copy2d(Vs, 1, q, y.cores[k - 1], t, 1, rows, t, 1.0, st);  // W_t
+        // H(Y_{k+1}) <- G_t^T H(Y_{k+1})
+        const int64_t nr = s.n[k] * r[k + 1];
+        double* nxt = carry[k & 1];
+        gemm(ws, st, t, (int)nr, b, G, b, 1, Z + off[k], nr, 1, nxt, nr, 1);
+        r[k] = t;
+        y.ranks[k] = t;
+        cur = nxt;
+    }
+    const int64_t last = r[d - 1] * s.n[d - 1];
+    if (last > y.cap[d - 1]) throw Error(-2, "output core " + std::to_string(d) + " exceeds its capacity");
+    TTR_HIP(hipMemcpyAsync(y.cores[d - 1], cur, (size_t)last * sizeof(double), hipMemcpyDeviceToDevice, st));
+    y.ranks[0] = 1;
+    y.ranks[d] = 1;
+    y.orth = 1;
+    TTR_HIP(hipStreamSynchronize(st));
+}
+
+// ---------------------------------------------------------------------------
 // Components
 // ---------------------------------------------------------------------------
 void gaussian_factor(uint64_t seed, int mode, int64_t n, int64_t col0, int64_t ncols, double* out,

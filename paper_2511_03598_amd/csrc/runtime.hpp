@@ -73,6 +73,10 @@ void round_fixed(const Shape& s, const double* const* cores, const int64_t* targ
                  uint64_t seed, const Options& o, OutCores& y, RoundInfo& info);
 void round_adaptive(const Shape& s, const double* const* cores, double tol, int64_t ell_block,
                     uint64_t seed, const Options& o, OutCores& y, RoundInfo& info);
+// Deterministic TT-SVD rounding (Sec. 2.3): tolerance tol, or target ranks
+// (host [d+1]) when target is given.
+void round_ttsvd(const Shape& s, const double* const* cores, double tol, const int64_t* target,
+                 const Options& o, OutCores& y, RoundInfo& info);
 
 // round_fixed with all device memory carved from `region` (region_bytes):
 // allocates nothing; the caller serialises calls that share a region.
