@@ -13,6 +13,9 @@ tensors rounded per second over the timed steps.  Printed beside it, in one JSON
   * the plain single-instance rate (one tt_round_adaptive call after the
     other on one stream, same tensors and seeds; the same ranks, tensors
     equal to rounding error) and the rate of the synchronous batch call;
+  * the same-GPU deterministic baseline: TT-SVD rounding (tt_round_ttsvd)
+    to the same tolerance on a systematic sample of the batch, its rate and
+    the batch's speed-up over it;
   * median / p10 / p90 of the step times;
   * sketch GB/s: the partial contractions' algorithmic bytes (one FP64
     read of each contracted core plus the W writes, every pass including
@@ -152,6 +155,8 @@ def main():
                          "left-to-right partial contractions of C2 (FP64, ell 60)")
     ap.add_argument("--count", type=int, default=256, help="c4: tensors in the batch")
     ap.add_argument("--plain-reps", type=int, default=3, help="c4: repetitions of the plain loop")
+    ap.add_argument("--ttsvd-sample", type=int, default=64,
+                    help="c4: tensors (systematic sample) rounded by the GPU TT-SVD for its rate")
     ap.add_argument("--no-plain", action="store_true",
                     help="c4: skip the plain loop and the synchronous batch call (profiling runs)")
     ap.add_argument("--requests", type=int, default=500, help="c5: requests per arrival rate")
@@ -269,6 +274,23 @@ def run_headline(args):
         torch.cuda.synchronize()
         plain_s.append(time.perf_counter() - t1)
     ranks_equal = None if plain is None else all(p[1]["ranks"] == b[1]["ranks"] for p, b in zip(plain, res))
+    # the same-GPU deterministic baseline: TT-SVD rounding (Sec. 2.3) to the
+    # same tolerance, one call after the other, on a systematic sample
+    ttsvd = None
+    if not args.no_plain and args.ttsvd_sample > 0:
+        sidx = c4_sample(len(xs), args.ttsvd_sample)
+        ttr.round_ttsvd(devs[sidx[0]], tol=C4_TOL)  # warm-up
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        sres = [ttr.round_ttsvd(devs[i], tol=C4_TOL) for i in sidx]
+        torch.cuda.synchronize()
+        svd_s = time.perf_counter() - t1
+        krp_rank = sum(sum(res[i][1]["ranks"]) for i in sidx)
+        svd_rank = sum(sum(r[1]["ranks"]) for r in sres)
+        ttsvd = {"value": len(sidx) / svd_s, "tensors": len(sidx), "seconds": svd_s,
+                 "rank_sum_krp_over_ttsvd": krp_rank / svd_rank,
+                 "sample": "systematic, every %d-th tensor of the batch" % max(1, len(xs) // len(sidx))}
+        log("TT-SVD: %d tensors in %.2f s" % (len(sidx), svd_s))
     # result of a sampled tensor alone vs in the batch (bitwise)
     j = len(xs) // 3
     alone = ttr.BatchPlan([devs[j]], C4_TOL, C4_BLOCK, [seeds[j]])
@@ -309,6 +331,9 @@ def run_headline(args):
         "plain_value": len(xs) / pctl(plain_s, 50) if plain_s else None,
         "plain_step_s": {"median": pctl(plain_s, 50), "reps": len(plain_s)} if plain_s else None,
         "speedup_vs_plain": pctl(plain_s, 50) / pctl(step_s, 50) if plain_s else None,
+        "ttsvd_value": ttsvd["value"] if ttsvd else None,
+        "speedup_vs_ttsvd": value / ttsvd["value"] if ttsvd else None,
+        "ttsvd": ttsvd,
         "ranks_equal_to_plain": ranks_equal,
         "alone_equals_in_batch": alone_same,
         "sketch_GBps": pc_bytes * args.steps / step_total / 1e9,
