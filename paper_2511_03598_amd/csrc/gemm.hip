@@ -415,7 +415,95 @@ void launch_direct(const GemmArgs& g, dim3 grid, int kchunk, double* partials, h
         launch_direct_k<BT, EXP, 16>(g, grid, kchunk, partials, s);
 }
 
+// ---------------------------------------------------------------------------
+// K-segmented product (launch_seg_gemm): a 32x32 output tile per workgroup,
+// wave w takes segments w, w+4, ... whole (the segment index is uniform per
+// wave, so its table entries are scalar loads), each in 64-deep chunks with
+// all operand loads of a chunk issued before its MFMAs; the four wave tiles
+// are added in LDS in a fixed order.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) seg_gemm_kernel(SegGemm g) {
+    __shared__ double red[4][32][33];
+    const int m0 = blockIdx.x * 32, n0 = blockIdx.y * 32;
+    const int lane = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int li = lane & 15, lg = lane >> 4;
+    int rows[2], cols[2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        rows[i] = min(m0 + 16 * i + li, g.M - 1);
+        cols[i] = min(n0 + 16 * i + li, g.N - 1);
+    }
+    double4_t acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = double4_t{0, 0, 0, 0};
+    for (int sg = w; sg < g.nseg; sg += 4) {
+        const double* A = g.A[sg];
+        const double* B = g.B[sg];
+        const int64_t lda = g.lda[sg], ldb = g.ldb[sg], ss = g.ss[sg];
+        const double al = g.alpha[sg];
+        const int K = g.K[sg], nsl = g.slices[sg];
+        for (int kb = 0; kb < K; kb += 64) {
+            double av[16][2], bv[16][2];
+#pragma unroll
+            for (int t = 0; t < 16; ++t) {
+                const int kc = min(kb + 4 * t + lg, K - 1);
+#pragma unroll
+                for (int i = 0; i < 2; ++i) {
+                    av[t][i] = A[(size_t)rows[i] * lda + kc];
+                    bv[t][i] = B[(size_t)cols[i] * ldb + kc];
+                }
+            }
+            for (int q = 1; q < nsl; ++q) {
+                const double* Bq = B + (size_t)q * ss;
+#pragma unroll
+                for (int t = 0; t < 16; ++t) {
+                    const int kc = min(kb + 4 * t + lg, K - 1);
+#pragma unroll
+                    for (int i = 0; i < 2; ++i) bv[t][i] += Bq[(size_t)cols[i] * ldb + kc];
+                }
+            }
+#pragma unroll
+            for (int t = 0; t < 16; ++t) {
+                if (kb + 4 * t < K) {  // uniform
+                    const bool kok = kb + 4 * t + lg < K;
+                    const double a0 = kok ? al * av[t][0] : 0.0, a1 = kok ? al * av[t][1] : 0.0;
+                    acc[0][0] = mfma_f64_16x16x4(a0, bv[t][0], acc[0][0]);
+                    acc[0][1] = mfma_f64_16x16x4(a0, bv[t][1], acc[0][1]);
+                    acc[1][0] = mfma_f64_16x16x4(a1, bv[t][0], acc[1][0]);
+                    acc[1][1] = mfma_f64_16x16x4(a1, bv[t][1], acc[1][1]);
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) red[w][16 * i + mfma_row_f64(lg, v)][16 * j + li] = acc[i][j][v];
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const int idx = threadIdx.x + 256 * e, r = idx & 31, c = idx >> 5;
+        const int row = m0 + r, col = n0 + c;
+        if (row < g.M && col < g.N)
+            g.C[(size_t)col * g.ldc + row] = ((red[0][r][c] + red[1][r][c]) + red[2][r][c]) + red[3][r][c];
+    }
+}
+
 }  // namespace
+
+void launch_seg_gemm(const SegGemm& g, hipStream_t s) {
+    if (g.M <= 0 || g.N <= 0) return;
+    if (g.nseg < 1 || g.nseg > kSegGemmMax) throw Error(-1, "segmented GEMM: 1..16 segments");
+    for (int i = 0; i < g.nseg; ++i)
+        if (g.K[i] < 1 || g.slices[i] < 1) throw Error(-1, "segmented GEMM: empty segment");
+    hipLaunchKernelGGL(seg_gemm_kernel, dim3(ceil_div(g.M, 32), ceil_div(g.N, 32)), dim3(256), 0, s, g);
+    TTR_CHECK_LAUNCH();
+}
 
 namespace {
 bool plain_direct(int M, int N, int K) {

@@ -46,10 +46,19 @@ struct PcArgs {
     int* out_maxexp;        // this launch's entries (r0 x ceil(nc/64) x slices)
     const int* in_colexp;   // colexp_{k+1} (nullptr at k=d)
     int* out_colexp;        // colexp_k
+    // FP64 only: terms > 1 contracts core k of `terms` TTs of the same shape
+    // in one launch; the cores, W_{k+1} and W_k of term i are Xt[i], Wnt[i]
+    // and Woutt[i] (device pointer tables; X, Wn and Wout then name term 0's
+    // for the argument checks), every term with the same strides.
+    int terms;
+    const double* const* Xt;
+    const void* const* Wnt;
+    void* const* Woutt;
 };
 // Number of K slices of the contraction of an r0 x n x r1 core (prec 0 FP64,
 // 1 FP32, 2 BF16); depends on the shape only, so every column block of W_k
-// is split the same way.
+// is split the same way.  A grouped launch of t terms uses
+// pc_slices(t r0, r1, 0).
 int pc_slices(int64_t r0, int64_t r1, int prec);
 void launch_pc_f64(const PcArgs& a, hipStream_t s);
 void launch_pc_f32(const PcArgs& a, hipStream_t s);
@@ -111,6 +120,27 @@ void launch_gemm(const GemmArgs& g, int splits, double* partials, hipStream_t s)
 // K slices launch_gemm uses for an M x N x K product; the caller provides
 // splits * M * N doubles of partials when this exceeds 1.
 int gemm_splits(int M, int N, int K);
+
+// Sum of products over K segments in one launch (the sketch of a sum of TTs
+// from its terms' W): C(m, n) = sum_s alpha_s sum_k A_s(m, k) B_s(k, n) for
+// m < M, n < N, with A_s(m, k) at A[s][m * lda[s] + k] and B_s(k, n) the sum
+// over slices q < slices[s] (in slice order) of B[s][q * ss[s] + n * ldb[s] +
+// k]; C column-major, C(m, n) at C[m + n * ldc], overwritten.
+constexpr int kSegGemmMax = 16;
+struct SegGemm {
+    int M, N, nseg;
+    double* C;
+    int64_t ldc;
+    int K[kSegGemmMax];
+    const double* A[kSegGemmMax];
+    int64_t lda[kSegGemmMax];
+    double alpha[kSegGemmMax];
+    const double* B[kSegGemmMax];
+    int64_t ldb[kSegGemmMax];
+    int slices[kSegGemmMax];
+    int64_t ss[kSegGemmMax];
+};
+void launch_seg_gemm(const SegGemm& g, hipStream_t s);
 
 // ---- small utilities (util.hip) --------------------------------------------
 // dst(i, j) = src(i, j) for a rows x cols matrix with arbitrary strides.

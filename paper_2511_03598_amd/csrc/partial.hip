@@ -81,8 +81,8 @@ __device__ __forceinline__ float bf16_to_f32(unsigned short h) {
 struct Slice {
     int kb0, kb1, rows16;
 };
-__device__ __forceinline__ Slice slice_of(int K) {
-    const int chunks = (K + 15) / 16, S = gridDim.z, h = blockIdx.z;
+__device__ __forceinline__ Slice slice_of(int K, int h, int S) {
+    const int chunks = (K + 15) / 16;
     const int c_lo = (h * chunks) / S, c_hi = ((h + 1) * chunks) / S;
     return Slice{16 * c_lo, min(K, 16 * c_hi), 16 * (c_hi - c_lo)};
 }
@@ -190,7 +190,10 @@ __global__ void __launch_bounds__(64 * NW, 8 / NW) pc_kernel(PcArgs p) {
     __shared__ T om_s[64 * OLD];
     __shared__ T red[NW][64];
     const int K = p.r1, n = p.n;
-    const Slice sl = slice_of(K);
+    // grid z: slices of one term, or (term, slice) pairs of a grouped launch
+    const int nt = max(p.terms, 1), S = gridDim.z / nt;
+    const int term = blockIdx.z / S, zs = blockIdx.z - term * S;
+    const Slice sl = slice_of(K, zs, S);
     const int nck = sl.rows16 / 16;
     const int a = blockIdx.x;
     const int tid = threadIdx.x, lane = tid & 63, wr = tid >> 6;
@@ -201,8 +204,8 @@ __global__ void __launch_bounds__(64 * NW, 8 / NW) pc_kernel(PcArgs p) {
     const bool has_k = wk1 > wk0;  // uniform per wave
     const int colbase = p.c0 + blockIdx.y * 64;
     const int ncb = min(64, p.c0 + p.nc - colbase);
-    const double* Xa = p.X + (size_t)a * n * K;
-    const T* Wn = static_cast<const T*>(p.Wn);
+    const double* Xa = (nt > 1 ? p.Xt[term] : p.X) + (size_t)a * n * K;
+    const T* Wn = static_cast<const T*>(nt > 1 ? p.Wnt[term] : p.Wn);
 
     // Omega tile rows rc..rc+63, columns colbase..colbase+63 (zero outside
     // n x ncb): thread -> one row, 8 consecutive columns
@@ -362,7 +365,7 @@ __global__ void __launch_bounds__(64 * NW, 8 / NW) pc_kernel(PcArgs p) {
         T v = (red[0][c] + red[1][c]) + (red[2][c] + red[3][c]);
         if (NW == 8) v += (red[4][c] + red[5][c]) + (red[6][c] + red[7][c]);
         if (SCALED) v *= (T)ldexp(1.0, -in_e);
-        T* Wo = static_cast<T*>(p.Wout) + blockIdx.z * p.out_ss;
+        T* Wo = static_cast<T*>(nt > 1 ? p.Woutt[term] : p.Wout) + zs * p.out_ss;
         if (c < ncb) Wo[(size_t)(colbase + c) * p.out_ld + a] = v;
         if (SCALED) track_exponents(p, a, colbase, c, ncb, (double)v, in_e);
     }
@@ -378,7 +381,7 @@ template <bool KEVEN, int WSCH>
 __global__ void __launch_bounds__(256, 2) pc_bf16_kernel(PcArgs p) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int K = p.r1, n = p.n;
-    const Slice sl = slice_of(K);
+    const Slice sl = slice_of(K, blockIdx.z, gridDim.z);
     const int LDK = sl.rows16 + 8;  // transposed row stride (bf16 elements)
     unsigned short* Wt = reinterpret_cast<unsigned short*>(smem_raw);  // 64 x LDK
     float* red = reinterpret_cast<float*>(Wt + (size_t)64 * LDK);       // [4][64]
@@ -585,9 +588,12 @@ void check_pc_args(const PcArgs& a, size_t esz) {
 template <typename T, bool SCALED>
 void launch_mfma(const PcArgs& a, hipStream_t s) {
     check_pc_args(a, sizeof(T));
-    const int S = pc_slices(a.r0, a.r1, sizeof(T) == 8 ? 0 : 1);
+    const int terms = std::max(a.terms, 1);
+    if (terms > 1 && (SCALED || !a.Xt || !a.Woutt || !a.Wnt))
+        throw Error(-6, "partial contraction: grouped terms need FP64 and pointer tables");
+    const int S = pc_slices((int64_t)a.r0 * terms, a.r1, sizeof(T) == 8 ? 0 : 1);
     const int rows16 = 16 * ceil_div(ceil_div(a.r1, 16), S);  // largest slice
-    const dim3 grid(a.r0, ceil_div(a.nc, 64), S);
+    const dim3 grid(a.r0, ceil_div(a.nc, 64), S * terms);
     // eight waves when the slices are long enough to give every chunk group work
     const bool ms = a.Wn != nullptr && a.in_slices > 1;
     const int nck = rows16 / 16;
@@ -628,6 +634,7 @@ void launch_pc_f32(const PcArgs& a, hipStream_t s) { launch_mfma<float, true>(a,
 
 void launch_pc_bf16(const PcArgs& a, hipStream_t s) {
     check_pc_args(a, 2);
+    if (a.terms > 1) throw Error(-6, "partial contraction: grouped terms need FP64");
     const int S = pc_slices(a.r0, a.r1, 2);
     const int rows16 = 16 * ceil_div(ceil_div(a.r1, 16), S);
     const size_t lds = (size_t)64 * (rows16 + 8) * 2 + (size_t)4 * 64 * 4;

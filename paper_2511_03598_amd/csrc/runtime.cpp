@@ -85,7 +85,7 @@ struct DevBuf {
 struct Workspace {
     int device = -1;
     DevBuf omega, w, colexp, maxexp, dn, doff, y0, y1, q, sbuf, tbuf, m, qrws, cqws, qrcnt, part, scal,
-        sumpart, sumcnt, small1, small2, small3, small4, tint, tmp, qrsticky, wq1, wq2;
+        sumpart, sumcnt, small1, small2, small3, small4, tint, tmp, qrsticky, wq1, wq2, ptab;
     // Deferred Householder fallback: while a rounding runs with lazy_qr set,
     // qr() launches only the CholeskyQR kernels and a breakdown sets the
     // device int qr_sticky; scalar readbacks fetch it too (host_int[1]) and
@@ -111,7 +111,7 @@ struct Workspace {
         host_int = reinterpret_cast<int*>(host + 32);
         for (DevBuf* b : {&omega, &w, &colexp, &maxexp, &dn, &doff, &y0, &y1, &q, &sbuf, &tbuf, &m, &qrws,
                           &cqws, &qrcnt, &part, &scal, &sumpart, &sumcnt, &small1, &small2, &small3,
-                          &small4, &tint, &tmp, &qrsticky, &wq1, &wq2})
+                          &small4, &tint, &tmp, &qrsticky, &wq1, &wq2, &ptab})
             b->arena = a;
     }
     ~Workspace() {
@@ -384,6 +384,12 @@ struct Sketch {
     std::vector<TermW> tw;
     double* om = nullptr;
     void* w = nullptr;
+    // FP64 sums whose terms share one shape: core k of every term is
+    // contracted in one launch (Xt, Wnt, Woutt per mode in ptab), and the
+    // slices are sized for the terms' rows together
+    bool grouped = false;
+    const void** ptab = nullptr;
+    std::vector<const void*> hptab;
     int* colexp = nullptr;
     int* maxexp = nullptr;
     int64_t* dn = nullptr;
@@ -411,6 +417,10 @@ struct Sketch {
         }
         const int64_t gy = (lcap + 63) / 64;
         int64_t wo = 0, mo = 0, co = 0;
+        grouped = prec == 0 && x.m() > 1 && x.m() <= kSegGemmMax;
+        for (int i = 1; grouped && i < x.m(); ++i)
+            grouped = x.sh[i].r == x.sh[0].r;
+        const int64_t gm = grouped ? x.m() : 1;
         tw.resize(x.m());
         for (int i = 0; i < x.m(); ++i) {
             const Shape& si = x.sh[i];
@@ -422,7 +432,7 @@ struct Sketch {
             t.sl.assign(d + 2, 1);
             for (int j = 2; j <= d; ++j) {
                 t.off[j] = wo;
-                t.sl[j] = pc_slices(si.r[j - 1], si.r[j], prec);
+                t.sl[j] = pc_slices(gm * si.r[j - 1], si.r[j], prec);
                 t.ld[j] = (si.r[j - 1] + 3) / 4 * 4;
                 t.ss[j] = t.ld[j] * lcap;
                 wo += t.sl[j] * t.ss[j];
@@ -435,6 +445,19 @@ struct Sketch {
         om = ws.omega.as<double>(o);
         const size_t esz = (prec == 0) ? sizeof(double) : (prec == 1 ? sizeof(float) : 2);
         w = ws.w.get(wo * esz);
+        if (grouped) {
+            // per mode k = 1..d: X_k of every term, then W_{k+1}, then W_k
+            const int m = x.m();
+            hptab.assign((size_t)3 * m * (d + 1), nullptr);
+            for (int k = 1; k <= d; ++k)
+                for (int i = 0; i < m; ++i) {
+                    hptab[(size_t)(3 * k + 0) * m + i] = x.cores[i][k - 1];
+                    hptab[(size_t)(3 * k + 1) * m + i] = k < d ? wk(i, k + 1) : nullptr;
+                    hptab[(size_t)(3 * k + 2) * m + i] = k >= 2 ? wk(i, k) : nullptr;
+                }
+            ptab = static_cast<const void**>(ws.ptab.get(hptab.size() * sizeof(void*)));
+            TTR_HIP(hipMemcpyAsync(ptab, hptab.data(), hptab.size() * sizeof(void*), hipMemcpyHostToDevice, st));
+        }
         if (prec != 0) {
             colexp = ws.colexp.as<int>(co);
             maxexp = ws.maxexp.as<int>(mo + 64);
@@ -481,8 +504,38 @@ struct Sketch {
         for (int j = t; j <= d; ++j) maxn = std::max(maxn, s.n[j - 1]);
         launch_omega(oa, d - t + 1, maxn, st);
         // one event pair around the back-to-back partial-contraction launches
-        TimedScope ts(KT_PC, st, (d - t + 1) * x.m());
-        for (int i = 0; i < x.m(); ++i) {
+        TimedScope ts(KT_PC, st, (d - t + 1) * (grouped ? 1 : x.m()));
+        if (grouped) {
+            const Shape& s0 = x.sh[0];
+            const TermW& t0 = tw[0];
+            const int m = x.m();
+            for (int k = d; k >= t; --k) {
+                PcArgs a{};
+                a.terms = m;
+                a.X = x.cores[0][k - 1];
+                a.Xt = reinterpret_cast<const double* const*>(ptab + (size_t)(3 * k + 0) * m);
+                a.r0 = (int)s0.r[k - 1];
+                a.n = (int)s0.n[k - 1];
+                a.r1 = (int)s0.r[k];
+                a.Om = omega(k);
+                a.ldo = lcap;
+                a.Wnt = ptab + (size_t)(3 * k + 1) * m;  // null entries at k = d
+                if (k < d) {
+                    a.Wn = wk(0, k + 1);
+                    a.in_ld = t0.ld[k + 1];
+                    a.in_ss = t0.ss[k + 1];
+                    a.in_slices = t0.sl[k + 1];
+                }
+                a.Wout = wk(0, k);
+                a.Woutt = const_cast<void* const*>(ptab + (size_t)(3 * k + 2) * m);
+                a.out_ld = t0.ld[k];
+                a.out_ss = t0.ss[k];
+                a.c0 = (int)ncols;
+                a.nc = (int)nc;
+                launch_pc_f64(a, st);
+            }
+        }
+        for (int i = 0; i < (grouped ? 0 : x.m()); ++i) {
             const Shape& si = x.sh[i];
             const TermW& tm = tw[i];
             for (int k = d; k >= t; --k) {
@@ -525,7 +578,7 @@ struct Sketch {
                 const double r0 = (double)si.r[k - 1], nk = (double)si.n[k - 1], r1 = (double)si.r[k];
                 pc_bytes += 8.0 * r0 * nk * r1 + esz * r0 * (double)nc;
                 pc_flops += 2.0 * r0 * nk * r1 * (double)nc + (k < d ? 2.0 * r0 * r1 * (double)nc : 0.0);
-                ++pc_launches;
+                if (!grouped || i == 0) ++pc_launches;
             }
         }
         ncols += nc;
@@ -543,6 +596,31 @@ struct Sketch {
     // S(rows x nb) = sum_i Z_i W^(i)_{k+1}(:, c0:c0+nb), S column-major (ld);
     // W is stored transposed (entry (b, c) at c * ld + b).
     void sketch_gemm(int k, const ZBlocks& zb, int rows, int64_t c0, int nb, double* S, int64_t ld) {
+        if (grouped) {
+            // every term in one launch: the products summed over the terms'
+            // K segments (with W sliced for the terms' rows together, most
+            // often one slice)
+            SegGemm g{};
+            g.M = rows;
+            g.N = nb;
+            g.nseg = x.m();
+            g.C = S;
+            g.ldc = ld;
+            for (int i = 0; i < x.m(); ++i) {
+                const TermW& tm = tw[i];
+                g.K[i] = (int)x.sh[i].r[k];
+                g.A[i] = zb.z[i];
+                g.lda[i] = zb.ldz[i];
+                g.alpha[i] = zb.zs[i];
+                g.B[i] = static_cast<const double*>(wk(i, k + 1)) + c0 * tm.ld[k + 1];
+                g.ldb[i] = tm.ld[k + 1];
+                g.slices[i] = tm.sl[k + 1];
+                g.ss[i] = tm.ss[k + 1];
+            }
+            TimedScope ts(KT_GEMM, st);
+            launch_seg_gemm(g, st);
+            return;
+        }
         for (int i = 0; i < x.m(); ++i) {
             const TermW& tm = tw[i];
             const int K = (int)x.sh[i].r[k];
