@@ -76,16 +76,27 @@ def sketch_bytes(dims, ranks, ell, w_bytes):
     return core + wout
 
 
+CSRC = os.path.join(ROOT, "paper_2511_03598_amd", "csrc")
 PMC_SUMMARY = os.path.join(ROOT, "profiles", "pc_kernel_c2_pmc.txt")
-PC_SOURCE = os.path.join(ROOT, "paper_2511_03598_amd", "csrc", "partial.hip")
+PC_SOURCES = [os.path.join(CSRC, "partial.hip")]
+BATCH_PMC_SUMMARY = os.path.join(ROOT, "profiles", "batch_kernel_c4_pmc.txt")
+BATCH_SOURCES = [os.path.join(CSRC, f) for f in ("batch.hip", "batch.hpp", "batch_host.cpp", "philox.hpp")]
 
 
-def pmc_traffic(path, alg_bytes_per_launch):
-    """HBM bytes per partial-contraction launch from a committed rocprofv3
-    FETCH_SIZE / WRITE_SIZE summary, or None when there is none or the
-    kernel source changed since it was taken (the summary records the
-    source's sha256)."""
+def source_digest(paths):
+    """sha256 over the kernel's source files, in order."""
     import hashlib
+    h = hashlib.sha256()
+    for p in paths:
+        h.update(open(p, "rb").read())
+    return h.hexdigest()
+
+
+def pmc_traffic(path, sources=PC_SOURCES):
+    """HBM bytes per launch from a committed rocprofv3 FETCH_SIZE /
+    WRITE_SIZE summary, or None when there is none or the kernel's source
+    changed since it was taken (the summary records source_sha256, the
+    digest of `sources`)."""
     try:
         text = open(path).read()
     except OSError:
@@ -95,8 +106,7 @@ def pmc_traffic(path, alg_bytes_per_launch):
         if "=" in line and not line.startswith("#"):
             k, v = line.split("=", 1)
             vals[k.strip()] = v.strip()
-    src = hashlib.sha256(open(PC_SOURCE, "rb").read()).hexdigest()
-    if vals.get("source_sha256") != src or "hbm_bytes_per_launch" not in vals:
+    if vals.get("source_sha256") != source_digest(sources) or "hbm_bytes_per_launch" not in vals:
         return None
     return float(vals["hbm_bytes_per_launch"])
 
@@ -338,7 +348,8 @@ def run_headline(args):
         "alone_equals_in_batch": alone_same,
         "sketch_GBps": pc_bytes * args.steps / step_total / 1e9,
         "roofline": roofline(bytes_step, flops_step, kern_s, FP64_MFMA_PEAK_TFLOPS,
-                             "persistent batched rounding (batch_kernel), whole rounding of the batch"),
+                             "persistent batched rounding (batch_kernel), whole rounding of the batch",
+                             pmc_traffic(BATCH_PMC_SUMMARY, BATCH_SOURCES)),
         "wall_s": wall,
     }
     out["roofline"]["launches_per_step"] = 1
@@ -382,7 +393,7 @@ def side_c2(args):
     return {"workload": c2_desc(), "roundings_per_s": 1.0 / pctl(times, 50),
             "roofline": roofline(b / per, info["pc_flops"] / per, ms / 1e3 / n, FP32_MFMA_PEAK_TFLOPS,
                                  "partial contraction, FP32 (pc_kernel<float>)",
-                                 pmc_traffic(PMC_SUMMARY, b / per)),
+                                 pmc_traffic(PMC_SUMMARY)),
             "sketch_GBps": b / (ms / 1e3 / args.steps) / 1e9, "ranks_max": max(info["ranks"])}
 
 
@@ -602,7 +613,7 @@ def run_c2(args):
         "sketch_GBps": pc_bytes / (pc_ms / 1e3 / args.steps) / 1e9,
         "roofline": roofline(pc_bytes / npc, info["pc_flops"] / npc, avg_launch_s,
                              FP32_MFMA_PEAK_TFLOPS, "partial contraction (pc_kernel<float>)",
-                             pmc_traffic(PMC_SUMMARY, pc_bytes / npc)),
+                             pmc_traffic(PMC_SUMMARY)),
         "kernel_ms_per_step": kbreak,
         "wall_s": wall,
     }
