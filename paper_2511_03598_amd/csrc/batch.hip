@@ -282,10 +282,20 @@ __device__ __noinline__ void wg_gemm(const double* A, int64_t ars, int64_t acs, 
 // B are loaded straight into MFMA layout, KS 4-deep K steps of loads issued
 // before their MFMAs; every load of the block precedes its stores, so C
 // may be A.
-template <int NB, int KS>
+// With GRAM the block's stored values X (16 rows x N, zero outside the
+// panel) are also accumulated into gram[] = the upper blocks (j1 <= j2) of
+// X^T X: a 16-row output tile in accumulator layout (lane l holds rows
+// l/16 + 4v of column l%16) is exactly the A and the B operand of its own
+// Gram product, four 4-deep steps over its rows.
+template <int NB>
+struct GramAcc {
+    double4_t g[NB * (NB + 1) / 2];
+};
+
+template <int NB, int KS, bool GRAM = false>
 __device__ __forceinline__ void rows_block(const double* A, int64_t ars, int64_t acs, const double* B, int64_t brs,
                                            int64_t bcs, double* C, int64_t crs, int64_t ccs, int r0, int re, int N,
-                                           int K, double alpha, double beta) {
+                                           int K, double alpha, double beta, GramAcc<NB>* gram = nullptr) {
     const int l = lane_id(), li = l & 15, lg = l >> 4;
     const int r = r0 + li;
     const bool vr = r < re;
@@ -321,18 +331,30 @@ __device__ __forceinline__ void rows_block(const double* A, int64_t ars, int64_t
 #pragma unroll
             for (int j = 0; j < NB; ++j) acc[j] = mfma_f64_16x16x4(a[s], b[s][j], acc[j]);
     }
+    double xs[NB][4];
 #pragma unroll
     for (int j = 0; j < NB; ++j)
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             const int rr = r0 + lg + 4 * v, c = 16 * j + li;
+            xs[j][v] = 0.0;
             if (rr < re && c < N) {
                 gdouble* p = gptr(C) + (int64_t)rr * crs + (int64_t)c * ccs;
                 double x = alpha * acc[j][v];
                 if (beta != 0.0) x += beta * *p;
                 *p = x;
+                xs[j][v] = x;
             }
         }
+    if (GRAM) {
+        int e = 0;
+#pragma unroll
+        for (int j1 = 0; j1 < NB; ++j1)
+#pragma unroll
+            for (int j2 = j1; j2 < NB; ++j2, ++e)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) gram->g[e] = mfma_f64_16x16x4(xs[j1][v], xs[j2][v], gram->g[e]);
+    }
 }
 
 // Row-split product of one member: its rows [rb, re) of a panel of N <= 64
@@ -350,6 +372,55 @@ __device__ __noinline__ void gemm_rows(const double* A, int64_t ars, int64_t acs
         else
             rows_block<4, 4>(A, ars, acs, B, brs, bcs, C, crs, ccs, r0, re, N, K, alpha, beta);
     }
+}
+
+// gemm_rows that also writes this member's partial Gram matrix of the
+// stored block, P (N x N, row-major) = sum over its rows [rb, re) of
+// C(r, i) C(r, j), the four wave partials added in wave order through LDS
+// (a member without rows writes zeros).  This replaces the Gram pass that
+// would otherwise read the block back.
+template <int NB, int KS>
+__device__ __forceinline__ void gemm_rows_gram_t(const double* A, int64_t ars, int64_t acs, const double* B,
+                                                 int64_t brs, int64_t bcs, double* C, int64_t crs, int64_t ccs, int rb,
+                                                 int re, int N, int K, double alpha, double beta, double* P,
+                                                 ldouble* lds) {
+    GramAcc<NB> ga;
+#pragma unroll
+    for (int e = 0; e < NB * (NB + 1) / 2; ++e) ga.g[e] = double4_t{0.0, 0.0, 0.0, 0.0};
+    for (int r0 = rb + 16 * wave_id(); r0 < re; r0 += 64)
+        rows_block<NB, KS, true>(A, ars, acs, B, brs, bcs, C, crs, ccs, r0, re, N, K, alpha, beta, &ga);
+    const int l = lane_id(), li = l & 15, lg = l >> 4, w = wave_id(), tid = threadIdx.x;
+    __syncthreads();  // the caller's LDS contents (a factor being read) are no longer needed
+    int e = 0;
+#pragma unroll
+    for (int j1 = 0; j1 < NB; ++j1)
+#pragma unroll
+        for (int j2 = j1; j2 < NB; ++j2, ++e) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) lds[w * 256 + (lg + 4 * v) * 16 + li] = ga.g[e][v];
+            __syncthreads();
+            {
+                const int r = tid >> 4, c = tid & 15;
+                const int gi = 16 * j1 + r, gj = 16 * j2 + c;
+                const double x = ((lds[tid] + lds[256 + tid]) + lds[512 + tid]) + lds[768 + tid];
+                if (gi < N && gj < N) {
+                    gptr(P)[(int64_t)gi * N + gj] = x;
+                    if (j1 != j2) gptr(P)[(int64_t)gj * N + gi] = x;
+                }
+            }
+            __syncthreads();
+        }
+}
+
+__device__ __noinline__ void gemm_rows_gram(const double* A, int64_t ars, int64_t acs, const double* B, int64_t brs,
+                                            int64_t bcs, double* C, int64_t crs, int64_t ccs, int rb, int re, int N,
+                                            int K, double alpha, double beta, double* P, ldouble* lds) {
+    if (N <= 16)
+        gemm_rows_gram_t<1, 16>(A, ars, acs, B, brs, bcs, C, crs, ccs, rb, re, N, K, alpha, beta, P, lds);
+    else if (N <= 32)
+        gemm_rows_gram_t<2, 8>(A, ars, acs, B, brs, bcs, C, crs, ccs, rb, re, N, K, alpha, beta, P, lds);
+    else
+        gemm_rows_gram_t<4, 4>(A, ars, acs, B, brs, bcs, C, crs, ccs, rb, re, N, K, alpha, beta, P, lds);
 }
 
 // P (Mo x No, row-major) = sum over k in [kb, ke) of A(i, k) B(k, j) for
@@ -641,15 +712,19 @@ __device__ __forceinline__ void count_event(const BatchTT* t, int m, int e) {
 // certificate failure (at most two), and a Householder QR by the first
 // member when a shifted factorization fails too or after six passes.  Each
 // member applies R^{-1} to its own rows [rb, re); the Householder route
-// ends with a team barrier, the others do not.
+// ends with a team barrier, the others do not.  have_gram: every member's
+// partial Gram matrix of S is already in its slot of parity par (written
+// with the block, see gemm_rows_gram); each R^{-1} application that a
+// further pass will factor writes the next Gram the same way.
 __device__ __noinline__ int qr_team(const BatchTT* t, int m, int par, double* S, int rows, int b, int rb, int re,
-                                    ldouble* lds) {
+                                    ldouble* lds, bool have_gram) {
     ldouble* G = lds;
     ldouble* misc = lds + kMisc;
     double* rinv = t->priv + (int64_t)m * t->privs;
     int plain_ok = 0, shifts = 0, passes = 0;
     for (;;) {
-        atb(S, rows, 1, b, S, 1, rows, b, rb, re, slot_of(t, par, m), lds);
+        if (!have_gram) atb(S, rows, 1, b, S, 1, rows, b, rb, re, slot_of(t, par, m), lds);
+        have_gram = false;
         team_sync(*t);
         const double* base = slots_base(t, par);
         par ^= 1;
@@ -683,15 +758,25 @@ __device__ __noinline__ int qr_team(const BatchTT* t, int m, int par, double* S,
             return par;
         }
         rinv_lds(G, b, rinv);
-        gemm_rows(S, 1, rows, rinv, b, 1, S, 1, rows, rb, re, b, b, 1.0, 0.0, lds);
-        __syncthreads();  // the next pass's Gram rows come from other waves' tiles
-        if (plain_ok >= 2) return par;
+        if (plain_ok >= 2) {
+            gemm_rows(S, 1, rows, rinv, b, 1, S, 1, rows, rb, re, b, b, 1.0, 0.0, lds);
+            __syncthreads();
+            return par;
+        }
+        // another pass follows: its Gram is formed while S is written
+        gemm_rows_gram(S, 1, rows, rinv, b, 1, S, 1, rows, rb, re, b, b, 1.0, 0.0, slot_of(t, par, m), lds);
+        __syncthreads();
+        have_gram = true;
     }
 }
 
 // S[own rows] -= Q[:, 0:ncq] (Q^T S), with Q^T S reduced over the team; S is
-// the rows x nb block that follows Q's ncq columns.  With want_sumsq the
-// team-reduced ||S||_F^2 after the update is returned in *ss.
+// the rows x nb block that follows Q's ncq columns.  The update also writes
+// each member's partial Gram matrix of the new S into its slot of the
+// returned parity (for qr_team with have_gram).  With want_sumsq the
+// team-reduced ||S||_F^2, the trace of that Gram matrix, is returned in *ss
+// after a team barrier; a caller that does not go on to qr_team must then
+// flip the parity before the slots are written again.
 __device__ __noinline__ int project_out(const BatchTT* t, int m, int par, double* Q, int rows, int ncq, int nb,
                                         int rb, int re, int want_sumsq, double* ss, ldouble* lds) {
     double* S = Q + (int64_t)ncq * rows;
@@ -701,17 +786,19 @@ __device__ __noinline__ int project_out(const BatchTT* t, int m, int par, double
     reduce_slots(slots_base(t, par), t->pslot, t->T, 0, ncq * nb, nb, tm, nb);
     par ^= 1;
     __syncthreads();
-    gemm_rows(Q, 1, rows, tm, nb, 1, S, 1, rows, rb, re, nb, ncq, -1.0, 1.0, lds);
+    gemm_rows_gram(Q, 1, rows, tm, nb, 1, S, 1, rows, rb, re, nb, ncq, -1.0, 1.0, slot_of(t, par, m), lds);
     __syncthreads();
     if (!want_sumsq) return par;
-    const double s = sumsq_rows(S, rows, nb, rb, re, lds + kMisc + kBatchMaxBlock + 12);
-    if (threadIdx.x == 0) slot_of(t, par, m)[0] = s;
     team_sync(*t);
     double tot = 0.0;
-    const double* base = slots_base(t, par);
-    for (int mm = 0; mm < t->T; ++mm) tot += base[(int64_t)mm * t->pslot];
+    const gdouble* base = gptr(slots_base(t, par));
+    for (int mm = 0; mm < t->T; ++mm) {
+        double tr = 0.0;
+        for (int i = 0; i < nb; ++i) tr += base[(int64_t)mm * t->pslot + (int64_t)i * nb + i];
+        tot += tr;
+    }
     *ss = tot;
-    return par ^ 1;
+    return par;
 }
 
 // Omega_j(:, c0:c0+nc) for modes j = j0..d, split over the team's threads.
@@ -898,11 +985,11 @@ __device__ __forceinline__ void round_tensor(const BatchTT* t, int m, ldouble* l
         member_rows(rows, T, m, rb, re);
         const double* Wk1 = t->w + t->woff[k + 1];
         tock(4);
-        // sketch of the first binit columns and its QR
-        gemm_rows(ycur, R, 1, Wk1, lcap, 1, Q, 1, rows, rb, re, binit, R, 1.0, 0.0, lds);
+        // sketch of the first binit columns (with its Gram matrix) and its QR
+        gemm_rows_gram(ycur, R, 1, Wk1, lcap, 1, Q, 1, rows, rb, re, binit, R, 1.0, 0.0, slot_of(t, par, m), lds);
         __syncthreads();
         tock(1);
-        par = qr_team(t, m, par, Q, rows, binit, rb, re, lds);
+        par = qr_team(t, m, par, Q, rows, binit, rb, re, lds, true);
         __syncthreads();
         tock(2);
         int ncq = binit;
@@ -926,13 +1013,16 @@ __device__ __forceinline__ void round_tensor(const BatchTT* t, int m, ldouble* l
             const double est = sqrt(ss / (double)bb);
             ++iterations;
             if (tau > 0.0) min_margin = fmin(min_margin, fabs(est - tau) / tau);
-            if (!(est > tau)) break;
-            par = qr_team(t, m, par, S, rows, bb, rb, re, lds);
+            if (!(est > tau)) {
+                par ^= 1;  // the block's Gram slots are not consumed
+                break;
+            }
+            par = qr_team(t, m, par, S, rows, bb, rb, re, lds, true);
             __syncthreads();
             tock(2);
             par = project_out(t, m, par, Q, rows, ncq, bb, rb, re, 0, &ss, lds);
             tock(3);
-            par = qr_team(t, m, par, S, rows, bb, rb, re, lds);
+            par = qr_team(t, m, par, S, rows, bb, rb, re, lds, true);
             __syncthreads();
             tock(2);
             ncq += bb;
