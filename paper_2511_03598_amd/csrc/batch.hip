@@ -993,6 +993,7 @@ __device__ __forceinline__ void round_tensor(const BatchTT* t, int m, ldouble* l
         __syncthreads();
         tock(2);
         int ncq = binit;
+        int sketched = binit;  // columns of Q's buffer that already hold V(Y_k) W_{k+1}
         const int blk = t->ell_block > 0 ? t->ell_block : max(1, (int)ceil(0.05 * (double)rbar));
         while (ncq < rbar) {
             const int bb = min(blk, rbar - ncq);
@@ -1004,8 +1005,15 @@ __device__ __forceinline__ void round_tensor(const BatchTT* t, int m, ldouble* l
                 tock(0);
             }
             double* S = Q + (int64_t)ncq * rows;
-            gemm_rows(ycur, R, 1, Wk1 + ncq, lcap, 1, S, 1, rows, rb, re, bb, R, 1.0, 0.0, lds);
-            __syncthreads();
+            if (sketched < need) {
+                // sketch up to 64 columns ahead in one pass over V(Y_k): a
+                // column's sketch does not depend on the basis, so the later
+                // blocks find theirs in place (unused ones are dropped)
+                const int nsk = max(bb, min(min(kBatchMaxBlock, rbar - ncq), ncols - ncq));
+                gemm_rows(ycur, R, 1, Wk1 + ncq, lcap, 1, S, 1, rows, rb, re, nsk, R, 1.0, 0.0, lds);
+                __syncthreads();
+                sketched = ncq + nsk;
+            }
             tock(1);
             double ss = 0.0;
             par = project_out(t, m, par, Q, rows, ncq, bb, rb, re, 1, &ss, lds);
