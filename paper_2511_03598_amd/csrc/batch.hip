@@ -712,12 +712,16 @@ __device__ __forceinline__ void count_event(const BatchTT* t, int m, int e) {
 // certificate failure (at most two), and a Householder QR by the first
 // member when a shifted factorization fails too or after six passes.  Each
 // member applies R^{-1} to its own rows [rb, re); the Householder route
-// ends with a team barrier, the others do not.  have_gram: every member's
+// ends with a team barrier, the others do not.  need_ok: plain (certified,
+// unshifted) passes that end the loop -- two for a general block, one for a
+// block that is already orthonormal to rounding error (after the
+// reorthogonalisation its Gram matrix is I + O(u), and one pass leaves it
+// orthonormal to O(u)).  have_gram: every member's
 // partial Gram matrix of S is already in its slot of parity par (written
 // with the block, see gemm_rows_gram); each R^{-1} application that a
 // further pass will factor writes the next Gram the same way.
 __device__ __noinline__ int qr_team(const BatchTT* t, int m, int par, double* S, int rows, int b, int rb, int re,
-                                    ldouble* lds, bool have_gram) {
+                                    ldouble* lds, bool have_gram, int need_ok = 2) {
     ldouble* G = lds;
     ldouble* misc = lds + kMisc;
     double* rinv = t->priv + (int64_t)m * t->privs;
@@ -758,7 +762,7 @@ __device__ __noinline__ int qr_team(const BatchTT* t, int m, int par, double* S,
             return par;
         }
         rinv_lds(G, b, rinv);
-        if (plain_ok >= 2) {
+        if (plain_ok >= need_ok) {
             gemm_rows(S, 1, rows, rinv, b, 1, S, 1, rows, rb, re, b, b, 1.0, 0.0, lds);
             __syncthreads();
             return par;
@@ -1030,7 +1034,7 @@ __device__ __forceinline__ void round_tensor(const BatchTT* t, int m, ldouble* l
             tock(2);
             par = project_out(t, m, par, Q, rows, ncq, bb, rb, re, 0, &ss, lds);
             tock(3);
-            par = qr_team(t, m, par, S, rows, bb, rb, re, lds, true);
+            par = qr_team(t, m, par, S, rows, bb, rb, re, lds, true, 1);
             __syncthreads();
             tock(2);
             ncq += bb;

@@ -82,6 +82,8 @@ def test_batch_c4_sample_vs_plain_and_oracle(lib):
         assert info["ranks"] == ip["ranks"]
         assert rel_tensor_diff(x, to_host(y), to_host(yp)) <= 1e-12
         assert tt.diff_norm(x, to_host(y)) <= 1e-6 * tt.norm(x)
+        # the blocks' final QR after reorthogonalisation is one CholeskyQR pass
+        assert tt.left_orth_defect(to_host(y)) < 1e-12
     # the oracle on the tensor with the largest team and two others
     for j in sorted(range(len(xs)), key=lambda j: -teams[j])[:1] + [0, 1]:
         say("  oracle, tensor", idx[j])
