@@ -169,7 +169,9 @@ __device__ __forceinline__ void track_exponents(const PcArgs& p, int a, int colb
 // four; FP64 (accumulators twice as wide) uses RT = 1.  WSCH chunks per
 // slab of operand loads; ONE: n <= 64 and every wave's chunks fit one slab,
 // so all operands are requested before the first MFMA and nothing later.
-// MS: W_{k+1} has more than one slice.
+// MS: W_{k+1} has more than one slice.  NBC: 16-column tiles of the output
+// block (launches of at most 48 columns use fewer than four, so no MFMA
+// works on padding columns).
 //
 // Omega's 64 x 64 tile for the row block is loaded once per workgroup
 // (coalesced, first), converted to T and kept in LDS for the fold.
@@ -180,7 +182,7 @@ __device__ __forceinline__ void track_exponents(const PcArgs& p, int a, int colb
 // end: scaling by a power of two commutes exactly with the products and
 // sums.
 // ---------------------------------------------------------------------------
-template <typename T, bool SCALED, bool KEVEN, int WSCH, int RT, int NW, bool MS, bool ONE>
+template <typename T, bool SCALED, bool KEVEN, int WSCH, int RT, int NW, bool MS, bool ONE, int NBC>
 __global__ void __launch_bounds__(64 * NW, 8 / NW) pc_kernel(PcArgs p) {
     constexpr int RG = 4 / RT;    // row groups
     constexpr int KGN = NW / RG;  // chunk groups
@@ -244,7 +246,7 @@ __global__ void __launch_bounds__(64 * NW, 8 / NW) pc_kernel(PcArgs p) {
 #pragma unroll
             for (int c = 0; c < WSCH; ++c)
 #pragma unroll
-                for (int nb = 0; nb < 4; ++nb) wb[c][nb] = v4{T(k0 + 16 * c + 4 * lg == 0), T(0), T(0), T(0)};
+                for (int nb = 0; nb < NBC; ++nb) wb[c][nb] = v4{T(k0 + 16 * c + 4 * lg == 0), T(0), T(0), T(0)};
             return;
         }
         const double* xr[RT];
@@ -252,7 +254,7 @@ __global__ void __launch_bounds__(64 * NW, 8 / NW) pc_kernel(PcArgs p) {
         for (int t = 0; t < RT; ++t) xr[t] = Xa + (size_t)min(rc + 16 * (RT * rg + t) + li, n - 1) * K;
         const T* wcol[4];
 #pragma unroll
-        for (int nb = 0; nb < 4; ++nb)
+        for (int nb = 0; nb < NBC; ++nb)
             wcol[nb] = Wn + (size_t)(colbase + min(16 * nb + li, ncb - 1)) * p.in_ld;
         const int bmax = (int)p.in_ld - 4;
 #pragma unroll
@@ -275,14 +277,14 @@ __global__ void __launch_bounds__(64 * NW, 8 / NW) pc_kernel(PcArgs p) {
             // 4 consecutive b of one column: one 16-byte load per chunk and
             // column tile in the transposed layout
 #pragma unroll
-            for (int nb = 0; nb < 4; ++nb) wb[c][nb] = *reinterpret_cast<const v4*>(wcol[nb] + min(kb, bmax));
+            for (int nb = 0; nb < NBC; ++nb) wb[c][nb] = *reinterpret_cast<const v4*>(wcol[nb] + min(kb, bmax));
         }
         if (MS) {
             for (int s = 1; s < p.in_slices; ++s)
 #pragma unroll
                 for (int c = 0; c < WSCH; ++c)
 #pragma unroll
-                    for (int nb = 0; nb < 4; ++nb)
+                    for (int nb = 0; nb < NBC; ++nb)
                         wb[c][nb] += *reinterpret_cast<const v4*>(wcol[nb] + s * p.in_ss +
                                                                   min(k0 + 16 * c + 4 * lg, bmax));
         }
@@ -308,7 +310,7 @@ __global__ void __launch_bounds__(64 * NW, 8 / NW) pc_kernel(PcArgs p) {
 #pragma unroll
         for (int t = 0; t < RT; ++t)
 #pragma unroll
-            for (int nb = 0; nb < 4; ++nb) acc[t][nb] = acc_t{0, 0, 0, 0};
+            for (int nb = 0; nb < NBC; ++nb) acc[t][nb] = acc_t{0, 0, 0, 0};
         if (has_k) {
             for (int k0 = wk0; ONE ? k0 == wk0 : k0 < wk1; k0 += 16 * WSCH) {
 #pragma unroll
@@ -325,7 +327,7 @@ __global__ void __launch_bounds__(64 * NW, 8 / NW) pc_kernel(PcArgs p) {
                             for (int t = 0; t < RT; ++t) {
                                 const T av = (T)xb[t][4 * c + s2];
 #pragma unroll
-                                for (int nb = 0; nb < 4; ++nb)
+                                for (int nb = 0; nb < NBC; ++nb)
                                     acc[t][nb] = Acc<T>::mma(av, kok ? wb[c][nb][s2] : T(0), acc[t][nb]);
                             }
                         }
@@ -347,20 +349,20 @@ __global__ void __launch_bounds__(64 * NW, 8 / NW) pc_kernel(PcArgs p) {
             for (int v = 0; v < 4; ++v) {
                 const T* orow = om_s + (16 * (RT * rg + t) + Acc<T>::row(lg, v)) * OLD + li;
 #pragma unroll
-                for (int nb = 0; nb < 4; ++nb) part[nb] += acc[t][nb][v] * orow[16 * nb];
+                for (int nb = 0; nb < NBC; ++nb) part[nb] += acc[t][nb][v] * orow[16 * nb];
             }
     }
 #pragma unroll
-    for (int nb = 0; nb < 4; ++nb) {
+    for (int nb = 0; nb < NBC; ++nb) {
         part[nb] += __shfl_xor(part[nb], 16, 64);
         part[nb] += __shfl_xor(part[nb], 32, 64);
     }
     if (lg == 0) {
 #pragma unroll
-        for (int nb = 0; nb < 4; ++nb) red[wr][nb * 16 + li] = part[nb];
+        for (int nb = 0; nb < NBC; ++nb) red[wr][nb * 16 + li] = part[nb];
     }
     __syncthreads();
-    if (tid < 64) {
+    if (tid < 64) {  // the whole first wave: track_exponents reduces over it
         const int c = tid;
         T v = (red[0][c] + red[1][c]) + (red[2][c] + red[3][c]);
         if (NW == 8) v += (red[4][c] + red[5][c]) + (red[6][c] + red[7][c]);
@@ -553,8 +555,8 @@ void allow_lds(K kern) {
     (void)attr;
 }
 
-template <typename T, bool SCALED, int NW, bool MS>
-void launch_mfma_nw(const PcArgs& a, const dim3& grid, int max_wave_chunks, hipStream_t s) {
+template <typename T, bool SCALED, int NW, bool MS, int NBC>
+void launch_mfma_nbc(const PcArgs& a, const dim3& grid, int max_wave_chunks, hipStream_t s) {
     // row tiles per wave and chunks per slab (register budget); when n <= 64
     // and every wave's chunks fit one slab of ONE_WS, all its operands are
     // requested at once
@@ -564,15 +566,30 @@ void launch_mfma_nw(const PcArgs& a, const dim3& grid, int max_wave_chunks, hipS
     const dim3 block(64 * NW);
     if (max_wave_chunks <= ONE_WS && a.n <= 64) {
         if (a.r1 % 2 == 0)
-            hipLaunchKernelGGL((pc_kernel<T, SCALED, true, ONE_WS, RT, NW, MS, true>), grid, block, 0, s, a);
+            hipLaunchKernelGGL((pc_kernel<T, SCALED, true, ONE_WS, RT, NW, MS, true, NBC>), grid, block, 0, s, a);
         else
-            hipLaunchKernelGGL((pc_kernel<T, SCALED, false, ONE_WS, RT, NW, MS, true>), grid, block, 0, s, a);
+            hipLaunchKernelGGL((pc_kernel<T, SCALED, false, ONE_WS, RT, NW, MS, true, NBC>), grid, block, 0, s, a);
     } else {
         if (a.r1 % 2 == 0)
-            hipLaunchKernelGGL((pc_kernel<T, SCALED, true, WS, RT, NW, MS, false>), grid, block, 0, s, a);
+            hipLaunchKernelGGL((pc_kernel<T, SCALED, true, WS, RT, NW, MS, false, NBC>), grid, block, 0, s, a);
         else
-            hipLaunchKernelGGL((pc_kernel<T, SCALED, false, WS, RT, NW, MS, false>), grid, block, 0, s, a);
+            hipLaunchKernelGGL((pc_kernel<T, SCALED, false, WS, RT, NW, MS, false, NBC>), grid, block, 0, s, a);
     }
+}
+
+template <typename T, bool SCALED, int NW, bool MS>
+void launch_mfma_nw(const PcArgs& a, const dim3& grid, int max_wave_chunks, hipStream_t s) {
+    // 16-column tiles: fewer than four only when the launch has one column
+    // block of at most 48 columns
+    const int nbc = a.nc > 48 ? 4 : std::max(1, ceil_div(a.nc, 16));
+    if (nbc == 1)
+        launch_mfma_nbc<T, SCALED, NW, MS, 1>(a, grid, max_wave_chunks, s);
+    else if (nbc == 2)
+        launch_mfma_nbc<T, SCALED, NW, MS, 2>(a, grid, max_wave_chunks, s);
+    else if (nbc == 3)
+        launch_mfma_nbc<T, SCALED, NW, MS, 3>(a, grid, max_wave_chunks, s);
+    else
+        launch_mfma_nbc<T, SCALED, NW, MS, 4>(a, grid, max_wave_chunks, s);
 }
 
 void check_pc_args(const PcArgs& a, size_t esz) {
