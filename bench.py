@@ -816,6 +816,7 @@ def run_c5(args):
     res = [srv.wait(t) for t in tk]
     t_sat = time.perf_counter() - t0
     mu = nsat / t_sat
+    log("c5 saturation: %d requests in %.2f s (%.2f/s)" % (nsat, t_sat, mu))
     runs = []
     for frac in (0.25, 0.5, 0.75, 0.9):
         lam = frac * mu
@@ -842,10 +843,13 @@ def run_c5(args):
             x, small = pick(i)
             nsmall += small
             pending.append((submit(x, 1000 + i), tnext))
+            if (i + 1) % 100 == 0:
+                log("c5 lambda %.2f mu: %d of %d submitted" % (frac, i + 1, args.requests))
         for (t, ta) in pending:
             r = srv.wait(t)
             lat.append(r[1]["done_s"] - r[1]["submit_s"])
         wall = time.perf_counter() - t0
+        log("c5 lambda %.2f mu done in %.1f s" % (frac, wall))
         lat = np.sort(np.array(lat))
         runs.append({"lambda_frac": frac, "lambda_per_s": lam, "requests": args.requests,
                      "small": nsmall, "p50_ms": float(np.percentile(lat, 50) * 1e3),
