@@ -277,11 +277,11 @@ __device__ __noinline__ void wg_gemm(const double* A, int64_t ars, int64_t acs, 
         wg_gemm_t<4>(A, ars, acs, B, brs, bcs, C, crs, ccs, rb, re, N, K, alpha, beta, g, G, lds);
 }
 
-// C[r0:r0+16, 0:N] = alpha A[r0:r0+16, 0:K] B[0:K, 0:N] + beta C for one
-// wave's 16-row block of a tall panel (N <= 16 NB): the block's A rows and
-// B are loaded straight into MFMA layout, KS 4-deep K steps of loads issued
-// before their MFMAs; every load of the block precedes its stores, so C
-// may be A.
+// C[r0:r0+16, 0:N] = alpha A[r0:r0+16, 0:K] B[0:K, 0:N] + beta C for each of
+// a wave's 16-row blocks of a tall panel (N <= 16 NB): A rows and B are
+// loaded straight into MFMA layout, KS 4-deep K steps of loads at a time;
+// every load of a block precedes its stores and other blocks' rows are
+// disjoint, so C may be A.
 // With GRAM the block's stored values X (16 rows x N, zero outside the
 // panel) are also accumulated into gram[] = the upper blocks (j1 <= j2) of
 // X^T X: a 16-row output tile in accumulator layout (lane l holds rows
@@ -293,13 +293,19 @@ struct GramAcc {
 };
 
 template <int NB, int KS, bool GRAM = false>
-__device__ __forceinline__ void rows_block(const double* A, int64_t ars, int64_t acs, const double* B, int64_t brs,
-                                           int64_t bcs, double* C, int64_t crs, int64_t ccs, int r0, int re, int N,
-                                           int K, double alpha, double beta, GramAcc<NB>* gram = nullptr) {
+__device__ __forceinline__ void rows_stream(const double* A, int64_t ars, int64_t acs, const double* B, int64_t brs,
+                                            int64_t bcs, double* C, int64_t crs, int64_t ccs, int rb, int re, int N,
+                                            int K, double alpha, double beta, GramAcc<NB>* gram = nullptr) {
+    // This wave's 16-row blocks r0 = rb + 16 w + 64 u in turn; each block's
+    // K range in steps of 4 KS.  The (block, step) sequence runs through two
+    // register stages, so the loads of the next step (possibly the next
+    // block's first) are in flight during the MFMAs of the current one; the
+    // per-block MFMA order and stores are those of one stage.
     const int l = lane_id(), li = l & 15, lg = l >> 4;
-    const int r = r0 + li;
-    const bool vr = r < re;
-    const gdouble* pa = gptr(A) + (int64_t)min(r, re - 1) * ars;
+    const int rfirst = rb + 16 * wave_id();
+    const int kit = (K + 4 * KS - 1) / (4 * KS);
+    const int nblk = (rfirst < re && K > 0) ? (re - rfirst + 63) / 64 : 0;
+    const int steps = nblk * kit;
     const gdouble* pb[NB];
     bool vb[NB];
 #pragma unroll
@@ -308,11 +314,13 @@ __device__ __forceinline__ void rows_block(const double* A, int64_t ars, int64_t
         vb[j] = c < N;
         pb[j] = gptr(B) + (int64_t)min(c, N - 1) * bcs;
     }
-    double4_t acc[NB];
-#pragma unroll
-    for (int j = 0; j < NB; ++j) acc[j] = double4_t{0.0, 0.0, 0.0, 0.0};
-    for (int k = 0; k < K; k += 4 * KS) {
-        double a[KS], b[KS][NB];
+    typedef double StageA[KS];
+    typedef double StageB[KS][NB];
+    auto load = [&](int st, StageA& a, StageB& b) {
+        const int blk = st / kit, k = (st - blk * kit) * 4 * KS;
+        const int r = rfirst + 64 * blk + li;
+        const bool vr = r < re;
+        const gdouble* pa = gptr(A) + (int64_t)min(r, re - 1) * ars;
 #pragma unroll
         for (int s = 0; s < KS; ++s) {
             const int kk = k + 4 * s + lg;
@@ -326,34 +334,60 @@ __device__ __forceinline__ void rows_block(const double* A, int64_t ars, int64_t
                 b[s][j] = (ok && vb[j]) ? u : 0.0;
             }
         }
+    };
+    double4_t acc[NB];
+#pragma unroll
+    for (int j = 0; j < NB; ++j) acc[j] = double4_t{0.0, 0.0, 0.0, 0.0};
+    auto mma = [&](const StageA& a, const StageB& b) {
 #pragma unroll
         for (int s = 0; s < KS; ++s)
 #pragma unroll
             for (int j = 0; j < NB; ++j) acc[j] = mfma_f64_16x16x4(a[s], b[s][j], acc[j]);
-    }
-    double xs[NB][4];
+    };
+    // after the last step of a block: its stores (and Gram products)
+    auto finish = [&](int blk) {
+        const int r0 = rfirst + 64 * blk;
+        double xs[NB][4];
 #pragma unroll
-    for (int j = 0; j < NB; ++j)
+        for (int j = 0; j < NB; ++j)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int rr = r0 + lg + 4 * v, c = 16 * j + li;
-            xs[j][v] = 0.0;
-            if (rr < re && c < N) {
-                gdouble* p = gptr(C) + (int64_t)rr * crs + (int64_t)c * ccs;
-                double x = alpha * acc[j][v];
-                if (beta != 0.0) x += beta * *p;
-                *p = x;
-                xs[j][v] = x;
+            for (int v = 0; v < 4; ++v) {
+                const int rr = r0 + lg + 4 * v, c = 16 * j + li;
+                xs[j][v] = 0.0;
+                if (rr < re && c < N) {
+                    gdouble* p = gptr(C) + (int64_t)rr * crs + (int64_t)c * ccs;
+                    double x = alpha * acc[j][v];
+                    if (beta != 0.0) x += beta * *p;
+                    *p = x;
+                    xs[j][v] = x;
+                }
             }
+        if (GRAM) {
+            int e = 0;
+#pragma unroll
+            for (int j1 = 0; j1 < NB; ++j1)
+#pragma unroll
+                for (int j2 = j1; j2 < NB; ++j2, ++e)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) gram->g[e] = mfma_f64_16x16x4(xs[j1][v], xs[j2][v], gram->g[e]);
         }
-    if (GRAM) {
-        int e = 0;
 #pragma unroll
-        for (int j1 = 0; j1 < NB; ++j1)
-#pragma unroll
-            for (int j2 = j1; j2 < NB; ++j2, ++e)
-#pragma unroll
-                for (int v = 0; v < 4; ++v) gram->g[e] = mfma_f64_16x16x4(xs[j1][v], xs[j2][v], gram->g[e]);
+        for (int j = 0; j < NB; ++j) acc[j] = double4_t{0.0, 0.0, 0.0, 0.0};
+    };
+    if (steps == 0) return;
+    StageA a0, a1;
+    StageB b0, b1;
+    load(0, a0, b0);
+    for (int st = 0; st < steps; st += 2) {  // uniform per wave
+        const bool more1 = st + 1 < steps, more2 = st + 2 < steps;
+        if (more1) load(st + 1, a1, b1);
+        mma(a0, b0);
+        if ((st + 1) % kit == 0) finish(st / kit);
+        if (more2) load(st + 2, a0, b0);
+        if (more1) {
+            mma(a1, b1);
+            if ((st + 2) % kit == 0) finish((st + 1) / kit);
+        }
     }
 }
 
@@ -364,14 +398,12 @@ __device__ __noinline__ void gemm_rows(const double* A, int64_t ars, int64_t acs
                                        double alpha, double beta, ldouble* lds) {
     (void)lds;
     if (re <= rb || N <= 0) return;
-    for (int r0 = rb + 16 * wave_id(); r0 < re; r0 += 64) {
-        if (N <= 16)
-            rows_block<1, 16>(A, ars, acs, B, brs, bcs, C, crs, ccs, r0, re, N, K, alpha, beta);
-        else if (N <= 32)
-            rows_block<2, 8>(A, ars, acs, B, brs, bcs, C, crs, ccs, r0, re, N, K, alpha, beta);
-        else
-            rows_block<4, 4>(A, ars, acs, B, brs, bcs, C, crs, ccs, r0, re, N, K, alpha, beta);
-    }
+    if (N <= 16)
+        rows_stream<1, 8>(A, ars, acs, B, brs, bcs, C, crs, ccs, rb, re, N, K, alpha, beta);
+    else if (N <= 32)
+        rows_stream<2, 4>(A, ars, acs, B, brs, bcs, C, crs, ccs, rb, re, N, K, alpha, beta);
+    else
+        rows_stream<4, 2>(A, ars, acs, B, brs, bcs, C, crs, ccs, rb, re, N, K, alpha, beta);
 }
 
 // gemm_rows that also writes this member's partial Gram matrix of the
@@ -387,8 +419,7 @@ __device__ __forceinline__ void gemm_rows_gram_t(const double* A, int64_t ars, i
     GramAcc<NB> ga;
 #pragma unroll
     for (int e = 0; e < NB * (NB + 1) / 2; ++e) ga.g[e] = double4_t{0.0, 0.0, 0.0, 0.0};
-    for (int r0 = rb + 16 * wave_id(); r0 < re; r0 += 64)
-        rows_block<NB, KS, true>(A, ars, acs, B, brs, bcs, C, crs, ccs, r0, re, N, K, alpha, beta, &ga);
+    rows_stream<NB, KS, true>(A, ars, acs, B, brs, bcs, C, crs, ccs, rb, re, N, K, alpha, beta, &ga);
     const int l = lane_id(), li = l & 15, lg = l >> 4, w = wave_id(), tid = threadIdx.x;
     __syncthreads();  // the caller's LDS contents (a factor being read) are no longer needed
     int e = 0;
@@ -416,11 +447,11 @@ __device__ __noinline__ void gemm_rows_gram(const double* A, int64_t ars, int64_
                                             int64_t bcs, double* C, int64_t crs, int64_t ccs, int rb, int re, int N,
                                             int K, double alpha, double beta, double* P, ldouble* lds) {
     if (N <= 16)
-        gemm_rows_gram_t<1, 16>(A, ars, acs, B, brs, bcs, C, crs, ccs, rb, re, N, K, alpha, beta, P, lds);
+        gemm_rows_gram_t<1, 8>(A, ars, acs, B, brs, bcs, C, crs, ccs, rb, re, N, K, alpha, beta, P, lds);
     else if (N <= 32)
-        gemm_rows_gram_t<2, 8>(A, ars, acs, B, brs, bcs, C, crs, ccs, rb, re, N, K, alpha, beta, P, lds);
+        gemm_rows_gram_t<2, 4>(A, ars, acs, B, brs, bcs, C, crs, ccs, rb, re, N, K, alpha, beta, P, lds);
     else
-        gemm_rows_gram_t<4, 4>(A, ars, acs, B, brs, bcs, C, crs, ccs, rb, re, N, K, alpha, beta, P, lds);
+        gemm_rows_gram_t<4, 2>(A, ars, acs, B, brs, bcs, C, crs, ccs, rb, re, N, K, alpha, beta, P, lds);
 }
 
 // P (Mo x No, row-major) = sum over k in [kb, ke) of A(i, k) B(k, j) for
@@ -460,8 +491,12 @@ __device__ __forceinline__ void atb_stream(const double* A, int64_t ars, int64_t
     for (int i = 0; i < MB; ++i)
 #pragma unroll
         for (int j = 0; j < NB; ++j) acc[i][j] = double4_t{0.0, 0.0, 0.0, 0.0};
-    for (int k = k0; k < k1; k += 4 * KS) {
-        double a[KS][MB], b[KS][NB];
+    // Two register stages: the loads of the next 4 KS rows of K are issued
+    // before the MFMAs of the current ones (same MFMA order as one stage,
+    // so the sums are unchanged).
+    typedef double StageA[KS][MB];
+    typedef double StageB[KS][NB];
+    auto load = [&](int k, StageA& a, StageB& b) {
 #pragma unroll
         for (int s = 0; s < KS; ++s) {
             const int kk = k + 4 * s + lg;
@@ -478,12 +513,24 @@ __device__ __forceinline__ void atb_stream(const double* A, int64_t ars, int64_t
                 b[s][j] = (ok && vb[j]) ? v : 0.0;
             }
         }
+    };
+    auto mma = [&](const StageA& a, const StageB& b) {
 #pragma unroll
         for (int s = 0; s < KS; ++s)
 #pragma unroll
             for (int i = 0; i < MB; ++i)
 #pragma unroll
                 for (int j = 0; j < NB; ++j) acc[i][j] = mfma_f64_16x16x4(a[s][i], b[s][j], acc[i][j]);
+    };
+    StageA a0, a1;
+    StageB b0, b1;
+    if (k0 < k1) load(k0, a0, b0);
+    for (int k = k0; k < k1; k += 8 * KS) {
+        const bool more1 = k + 4 * KS < k1, more2 = k + 8 * KS < k1;  // uniform
+        if (more1) load(k + 4 * KS, a1, b1);
+        mma(a0, b0);
+        if (more2) load(k + 8 * KS, a0, b0);
+        if (more1) mma(a1, b1);
     }
     // wave partials of each block through LDS, added in wave order
 #pragma unroll
@@ -512,11 +559,11 @@ __device__ __noinline__ void atb(const double* A, int64_t ars, int64_t acs, int 
         for (int i0 = 0; i0 < Mo; i0 += 128) {
             const int mb = (min(Mo - i0, 128) + 15) / 16;
             if (mb <= 1)
-                atb_stream<1, 1, 16>(A, ars, acs, Mo, B, brs, bcs, No, kb, ke, i0, 0, P, lds);
+                atb_stream<1, 1, 8>(A, ars, acs, Mo, B, brs, bcs, No, kb, ke, i0, 0, P, lds);
             else if (mb <= 2)
                 atb_stream<2, 1, 8>(A, ars, acs, Mo, B, brs, bcs, No, kb, ke, i0, 0, P, lds);
             else if (mb <= 4)
-                atb_stream<4, 1, 8>(A, ars, acs, Mo, B, brs, bcs, No, kb, ke, i0, 0, P, lds);
+                atb_stream<4, 1, 4>(A, ars, acs, Mo, B, brs, bcs, No, kb, ke, i0, 0, P, lds);
             else
                 atb_stream<8, 1, 2>(A, ars, acs, Mo, B, brs, bcs, No, kb, ke, i0, 0, P, lds);
         }
