@@ -65,6 +65,9 @@ constexpr uint64_t kSpinTicks = 500000000ull;                  // 5 s of the 100
 // compile to global_* instructions (counted by vmcnt alone) instead of
 // flat_* ones, which the compiler must also count as LDS accesses.
 typedef __attribute__((address_space(1))) double gdouble;
+// two doubles at an 8-byte aligned address (one 16-byte global load)
+typedef double d2u __attribute__((ext_vector_type(2), aligned(8)));
+typedef __attribute__((address_space(1))) d2u gd2u;
 __device__ __forceinline__ const gdouble* gptr(const double* p) { return (const gdouble*)p; }
 __device__ __forceinline__ gdouble* gptr(double* p) { return (gdouble*)p; }
 
@@ -492,25 +495,48 @@ __device__ __forceinline__ void atb_stream(const double* A, int64_t ars, int64_t
 #pragma unroll
         for (int j = 0; j < NB; ++j) acc[i][j] = double4_t{0.0, 0.0, 0.0, 0.0};
     // Two register stages: the loads of the next 4 KS rows of K are issued
-    // before the MFMAs of the current ones (same MFMA order as one stage,
-    // so the sums are unchanged).
+    // before the MFMAs of the current ones.  K steps go in pairs: in the
+    // pair at base, lane group lg holds rows base + 2 lg (first step) and
+    // base + 2 lg + 1 (second), so an operand contiguous along K (a
+    // column-major panel) is one 16-byte load per lane and pair.
+    static_assert(KS % 2 == 0, "K steps come in pairs");
     typedef double StageA[KS][MB];
     typedef double StageB[KS][NB];
+    const bool acont = acs == 1, bcont = brs == 1;
     auto load = [&](int k, StageA& a, StageB& b) {
+        const bool whole = k + 4 * KS <= k1;  // uniform: no row of the step past k1
 #pragma unroll
-        for (int s = 0; s < KS; ++s) {
-            const int kk = k + 4 * s + lg;
-            const bool ok = kk < k1;
-            const int64_t kc = min(kk, k1 - 1);
+        for (int q = 0; q < KS / 2; ++q) {
+            const int kk = k + 8 * q + 2 * lg;
+            const bool ok0 = kk < k1, ok1 = kk + 1 < k1;
+            const int64_t kc0 = min(kk, k1 - 1), kc1 = min(kk + 1, k1 - 1);
 #pragma unroll
             for (int i = 0; i < MB; ++i) {
-                const double v = pa[i][kc * acs];
-                a[s][i] = (ok && va[i]) ? v : 0.0;
+                double v0, v1;
+                if (acont && whole) {
+                    const d2u v = *(const gd2u*)(pa[i] + kk);
+                    v0 = v[0];
+                    v1 = v[1];
+                } else {
+                    v0 = pa[i][kc0 * acs];
+                    v1 = pa[i][kc1 * acs];
+                }
+                a[2 * q][i] = (ok0 && va[i]) ? v0 : 0.0;
+                a[2 * q + 1][i] = (ok1 && va[i]) ? v1 : 0.0;
             }
 #pragma unroll
             for (int j = 0; j < NB; ++j) {
-                const double v = pb[j][kc * brs];
-                b[s][j] = (ok && vb[j]) ? v : 0.0;
+                double v0, v1;
+                if (bcont && whole) {
+                    const d2u v = *(const gd2u*)(pb[j] + kk);
+                    v0 = v[0];
+                    v1 = v[1];
+                } else {
+                    v0 = pb[j][kc0 * brs];
+                    v1 = pb[j][kc1 * brs];
+                }
+                b[2 * q][j] = (ok0 && vb[j]) ? v0 : 0.0;
+                b[2 * q + 1][j] = (ok1 && vb[j]) ? v1 : 0.0;
             }
         }
     };
@@ -564,6 +590,8 @@ __device__ __noinline__ void atb(const double* A, int64_t ars, int64_t acs, int 
                 atb_stream<2, 1, 8>(A, ars, acs, Mo, B, brs, bcs, No, kb, ke, i0, 0, P, lds);
             else if (mb <= 4)
                 atb_stream<4, 1, 4>(A, ars, acs, Mo, B, brs, bcs, No, kb, ke, i0, 0, P, lds);
+            else if (mb <= 6)
+                atb_stream<6, 1, 2>(A, ars, acs, Mo, B, brs, bcs, No, kb, ke, i0, 0, P, lds);
             else
                 atb_stream<8, 1, 2>(A, ars, acs, Mo, B, brs, bcs, No, kb, ke, i0, 0, P, lds);
         }
