@@ -317,24 +317,40 @@ __device__ __forceinline__ void rows_stream(const double* A, int64_t ars, int64_
         vb[j] = c < N;
         pb[j] = gptr(B) + (int64_t)min(c, N - 1) * bcs;
     }
+    // K steps in pairs as in atb_stream: lane group lg holds rows base +
+    // 2 lg and base + 2 lg + 1 of the pair at base, so an A contiguous along
+    // K (a row-major panel) is one 16-byte load per lane and pair
+    static_assert(KS % 2 == 0, "K steps come in pairs");
     typedef double StageA[KS];
     typedef double StageB[KS][NB];
+    const bool acont = acs == 1;
     auto load = [&](int st, StageA& a, StageB& b) {
         const int blk = st / kit, k = (st - blk * kit) * 4 * KS;
         const int r = rfirst + 64 * blk + li;
         const bool vr = r < re;
+        const bool whole = k + 4 * KS <= K;  // uniform
         const gdouble* pa = gptr(A) + (int64_t)min(r, re - 1) * ars;
 #pragma unroll
-        for (int s = 0; s < KS; ++s) {
-            const int kk = k + 4 * s + lg;
-            const bool ok = kk < K;
-            const int64_t kc = min(kk, K - 1);
-            const double v = pa[kc * acs];
-            a[s] = (ok && vr) ? v : 0.0;
+        for (int q = 0; q < KS / 2; ++q) {
+            const int kk = k + 8 * q + 2 * lg;
+            const bool ok0 = kk < K, ok1 = kk + 1 < K;
+            const int64_t kc0 = min(kk, K - 1), kc1 = min(kk + 1, K - 1);
+            double v0, v1;
+            if (acont && whole) {
+                const d2u v = *(const gd2u*)(pa + kk);
+                v0 = v[0];
+                v1 = v[1];
+            } else {
+                v0 = pa[kc0 * acs];
+                v1 = pa[kc1 * acs];
+            }
+            a[2 * q] = (ok0 && vr) ? v0 : 0.0;
+            a[2 * q + 1] = (ok1 && vr) ? v1 : 0.0;
 #pragma unroll
             for (int j = 0; j < NB; ++j) {
-                const double u = pb[j][kc * brs];
-                b[s][j] = (ok && vb[j]) ? u : 0.0;
+                const double u0 = pb[j][kc0 * brs], u1 = pb[j][kc1 * brs];
+                b[2 * q][j] = (ok0 && vb[j]) ? u0 : 0.0;
+                b[2 * q + 1][j] = (ok1 && vb[j]) ? u1 : 0.0;
             }
         }
     };
