@@ -148,9 +148,18 @@ __device__ __forceinline__ void slab_load(const Panel& P, int r0, int k, int k1,
         const int r = tid >> 2, kq = (tid & 3) * 4;
         const int gr = r0 + r;
         const int64_t base = (int64_t)min(gr, P.R - 1) * P.rs;
+        const int gk0 = k + kq;
+        if (gr < P.R && gk0 + 4 <= k1) {  // four in-range neighbours: two 16-byte loads
+            const d2u v0 = *(const gd2u*)(g + base + gk0), v1 = *(const gd2u*)(g + base + gk0 + 2);
+            s.v[0] = v0[0];
+            s.v[1] = v0[1];
+            s.v[2] = v1[0];
+            s.v[3] = v1[1];
+            return;
+        }
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            const int gk = k + kq + q;
+            const int gk = gk0 + q;
             const double v = g[base + min(gk, k1 - 1)];
             s.v[q] = (gr < P.R && gk < k1) ? v : 0.0;
         }
@@ -158,9 +167,18 @@ __device__ __forceinline__ void slab_load(const Panel& P, int r0, int k, int k1,
         const int kk = tid >> 4, rq = (tid & 15) * 4;
         const int gk = k + kk;
         const int64_t kb = (int64_t)min(gk, k1 - 1) * P.cs;
+        const int gr0 = r0 + rq;
+        if (P.rs == 1 && gk < k1 && gr0 + 4 <= P.R) {  // four consecutive rows in one column
+            const d2u v0 = *(const gd2u*)(g + gr0 + kb), v1 = *(const gd2u*)(g + gr0 + 2 + kb);
+            s.v[0] = v0[0];
+            s.v[1] = v0[1];
+            s.v[2] = v1[0];
+            s.v[3] = v1[1];
+            return;
+        }
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            const int gr = r0 + rq + q;
+            const int gr = gr0 + q;
             const double v = g[(int64_t)min(gr, P.R - 1) * P.rs + kb];
             s.v[q] = (gr < P.R && gk < k1) ? v : 0.0;
         }
