@@ -341,9 +341,22 @@ __device__ __forceinline__ void rows_stream(const double* A, int64_t ars, int64_
     static_assert(KS % 2 == 0, "K steps come in pairs");
     typedef double StageA[KS];
     typedef double StageB[KS][NB];
+    typedef double StageC[NB][4];
     const bool acont = acs == 1;
-    auto load = [&](int st, StageA& a, StageB& b) {
-        const int blk = st / kit, k = (st - blk * kit) * 4 * KS;
+    // with beta != 0 a block's last step also loads the C entries its
+    // stores update, so no store waits for a load of its own
+    auto load = [&](int st, StageA& a, StageB& b, StageC& cv) {
+        const int blk = st / kit, ki = st - blk * kit, k = ki * 4 * KS;
+        if (beta != 0.0 && ki == kit - 1) {  // uniform
+            const int r0 = rfirst + 64 * blk;
+#pragma unroll
+            for (int j = 0; j < NB; ++j)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int rr = min(r0 + lg + 4 * v, re - 1), c = min(16 * j + li, N - 1);
+                    cv[j][v] = gptr(C)[(int64_t)rr * crs + (int64_t)c * ccs];
+                }
+        }
         const int r = rfirst + 64 * blk + li;
         const bool vr = r < re;
         const bool whole = k + 4 * KS <= K;  // uniform
@@ -382,7 +395,7 @@ __device__ __forceinline__ void rows_stream(const double* A, int64_t ars, int64_
             for (int j = 0; j < NB; ++j) acc[j] = mfma_f64_16x16x4(a[s], b[s][j], acc[j]);
     };
     // after the last step of a block: its stores (and Gram products)
-    auto finish = [&](int blk) {
+    auto finish = [&](int blk, const StageC& cv) {
         const int r0 = rfirst + 64 * blk;
         double xs[NB][4];
 #pragma unroll
@@ -392,10 +405,9 @@ __device__ __forceinline__ void rows_stream(const double* A, int64_t ars, int64_
                 const int rr = r0 + lg + 4 * v, c = 16 * j + li;
                 xs[j][v] = 0.0;
                 if (rr < re && c < N) {
-                    gdouble* p = gptr(C) + (int64_t)rr * crs + (int64_t)c * ccs;
                     double x = alpha * acc[j][v];
-                    if (beta != 0.0) x += beta * *p;
-                    *p = x;
+                    if (beta != 0.0) x += beta * cv[j][v];
+                    gptr(C)[(int64_t)rr * crs + (int64_t)c * ccs] = x;
                     xs[j][v] = x;
                 }
             }
@@ -414,16 +426,17 @@ __device__ __forceinline__ void rows_stream(const double* A, int64_t ars, int64_
     if (steps == 0) return;
     StageA a0, a1;
     StageB b0, b1;
-    load(0, a0, b0);
+    StageC c0, c1;
+    load(0, a0, b0, c0);
     for (int st = 0; st < steps; st += 2) {  // uniform per wave
         const bool more1 = st + 1 < steps, more2 = st + 2 < steps;
-        if (more1) load(st + 1, a1, b1);
+        if (more1) load(st + 1, a1, b1, c1);
         mma(a0, b0);
-        if ((st + 1) % kit == 0) finish(st / kit);
-        if (more2) load(st + 2, a0, b0);
+        if ((st + 1) % kit == 0) finish(st / kit, c0);
+        if (more2) load(st + 2, a0, b0, c0);
         if (more1) {
             mma(a1, b1);
-            if ((st + 2) % kit == 0) finish((st + 1) / kit);
+            if ((st + 2) % kit == 0) finish((st + 1) / kit, c1);
         }
     }
 }
@@ -435,7 +448,9 @@ __device__ __noinline__ void gemm_rows(const double* A, int64_t ars, int64_t acs
                                        double alpha, double beta, ldouble* lds) {
     (void)lds;
     if (re <= rb || N <= 0) return;
-    if (N <= 16)
+    if (N <= 16 && K <= 16)  // one 16-deep step per block
+        rows_stream<1, 4>(A, ars, acs, B, brs, bcs, C, crs, ccs, rb, re, N, K, alpha, beta);
+    else if (N <= 16)
         rows_stream<1, 8>(A, ars, acs, B, brs, bcs, C, crs, ccs, rb, re, N, K, alpha, beta);
     else if (N <= 32)
         rows_stream<2, 4>(A, ars, acs, B, brs, bcs, C, crs, ccs, rb, re, N, K, alpha, beta);
@@ -483,7 +498,9 @@ __device__ __forceinline__ void gemm_rows_gram_t(const double* A, int64_t ars, i
 __device__ __noinline__ void gemm_rows_gram(const double* A, int64_t ars, int64_t acs, const double* B, int64_t brs,
                                             int64_t bcs, double* C, int64_t crs, int64_t ccs, int rb, int re, int N,
                                             int K, double alpha, double beta, double* P, ldouble* lds) {
-    if (N <= 16)
+    if (N <= 16 && K <= 16)  // one 16-deep step per block
+        gemm_rows_gram_t<1, 4>(A, ars, acs, B, brs, bcs, C, crs, ccs, rb, re, N, K, alpha, beta, P, lds);
+    else if (N <= 16)
         gemm_rows_gram_t<1, 8>(A, ars, acs, B, brs, bcs, C, crs, ccs, rb, re, N, K, alpha, beta, P, lds);
     else if (N <= 32)
         gemm_rows_gram_t<2, 4>(A, ars, acs, B, brs, bcs, C, crs, ccs, rb, re, N, K, alpha, beta, P, lds);
@@ -1041,12 +1058,27 @@ __device__ __noinline__ int project_and_next(const BatchTT* t, int m, int par, i
     const int T = t->T;
     double* Q = t->q;
     atb(Q, rows, 1, lk, ycur, R, 1, R, rb, re, slot_of(t, par, m), lds);
+    // this member's rows of Q (column-major) into the output core
+    // (row-major), through LDS in 64 x 32 tiles so that both the reads and
+    // the writes are contiguous
     gdouble* Yk = gptr(t->Y[k - 1]);
     const gdouble* Qg = gptr(Q);
-    for (int64_t e = threadIdx.x; e < (int64_t)(re - rb) * lk; e += 256) {
-        const int64_t c = e / (re - rb), r = rb + (e - c * (re - rb));
-        Yk[r * lk + c] = Qg[c * rows + r];
-    }
+    for (int r0 = rb; r0 < re; r0 += 64)
+        for (int c0 = 0; c0 < lk; c0 += 32) {
+            const int nr = min(64, re - r0), ncc = min(32, lk - c0);
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {  // read: thread -> row tid % 64, column tid / 64 + 4 u
+                const int r = threadIdx.x & 63, c = (threadIdx.x >> 6) + 4 * u;
+                if (r < nr && c < ncc) lds[c * 65 + r] = Qg[(int64_t)(c0 + c) * rows + r0 + r];
+            }
+            __syncthreads();
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {  // write: thread -> column tid % 32, row tid / 32 + 8 u
+                const int c = threadIdx.x & 31, r = (threadIdx.x >> 5) + 8 * u;
+                if (r < nr && c < ncc) Yk[(int64_t)(r0 + r) * lk + c0 + c] = lds[c * 65 + r];
+            }
+            __syncthreads();
+        }
     team_sync(*t);
     const int E = lk * R;
     reduce_slots(slots_base(t, par), t->pslot, T, (int)((int64_t)E * m / T), (int)((int64_t)E * (m + 1) / T), R,
