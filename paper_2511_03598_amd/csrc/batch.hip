@@ -951,42 +951,123 @@ __device__ __noinline__ void gen_omega(const BatchTT* t, int m, int j0, int c0, 
 // one row a, by the workgroup: the core row times W_{k+1} as MFMA tiles,
 // each folded with Omega_k in registers (fixed order over i), then the
 // lane groups by two butterflies and the waves in wave order through LDS.
-template <int TN>
-__device__ __forceinline__ void pc_row(const double* Xa, int n, int r1, const double* Wn, int lcap, const double* Om,
-                                       int nc, double* out, ldouble* lds) {
-    const int l = lane_id(), li = l & 15, lg = l >> 4, w = wave_id(), tid = threadIdx.x;
-    constexpr int tw = 16 * TN;
-    const Panel PA{Xa, r1, 1, n};
-    const Panel PB{Wn, 1, lcap, nc};
-    for (int n0 = 0; n0 < nc; n0 += tw) {
-        double part[TN];
+// Rows a = a0, a0 + astep, ... of W_k for one wave (Sec. 3.1, Eq. 8):
+// W_k(a, c) = sum_i Omega_k(i, c) sum_b X_k(a, i, b) W_{k+1}(b, c).  For
+// each row, 16-row blocks i0 of X_k(a) (n x r1, rows contiguous in b) are
+// multiplied by W_{k+1} (r1 x nc, row stride lcap) over K = r1 in steps of
+// 4 KS, and each finished block is folded with Omega_k(i0.., c) into the
+// lane's partial sums; a row's sums are reduced over the lane groups and
+// stored.  The wave's (row, block, step) sequence runs through two
+// register stages, and a block's last step also loads its Omega entries,
+// so no MFMA or fold waits for a load issued just before it.  K steps are
+// paired as in atb_stream (16-byte loads of a core row).
+template <int NB, int KS>
+__device__ __forceinline__ void pc_stream(const double* X, int r0, int n, int r1, const double* Wn, int lcap,
+                                          const double* Om, int nc, double* W, int a0, int astep) {
+    static_assert(KS % 2 == 0, "K steps come in pairs");
+    const int l = lane_id(), li = l & 15, lg = l >> 4;
+    const int nrow = a0 < r0 ? (r0 - a0 + astep - 1) / astep : 0;
+    const int nbk = (n + 15) / 16, kit = (r1 + 4 * KS - 1) / (4 * KS), per_row = nbk * kit;
+    const int steps = nrow * per_row;
+    if (steps == 0) return;
+    const gdouble* pb[NB];
+    bool vb[NB];
 #pragma unroll
-        for (int j = 0; j < TN; ++j) part[j] = 0.0;
-        for (int m0 = 0; m0 < n; m0 += 64) {
-            double4_t acc[TN];
-            zero_acc(acc);
-            wg_tile<TN>(PA, PB, m0, n0, 0, r1, acc, lds);
+    for (int j = 0; j < NB; ++j) {
+        const int c = 16 * j + li;
+        vb[j] = c < nc;
+        pb[j] = gptr(Wn) + min(c, nc - 1);
+    }
+    typedef double StageA[KS];
+    typedef double StageB[KS][NB];
+    typedef double StageO[NB][4];
+    auto load = [&](int st, StageA& a, StageB& b, StageO& o) {
+        const int u = st / per_row, rem = st - u * per_row, bk = rem / kit, ki = rem - bk * kit;
+        const int row = a0 + astep * u, i = 16 * bk + li, k = 4 * KS * ki;
+        const bool vi = i < n, whole = k + 4 * KS <= r1;  // whole: uniform
+        const gdouble* pa = gptr(X) + ((int64_t)row * n + min(i, n - 1)) * r1;
 #pragma unroll
-            for (int j = 0; j < TN; ++j)
+        for (int q = 0; q < KS / 2; ++q) {
+            const int kk = k + 8 * q + 2 * lg;
+            const bool ok0 = kk < r1, ok1 = kk + 1 < r1;
+            const int kc0 = min(kk, r1 - 1), kc1 = min(kk + 1, r1 - 1);
+            double v0, v1;
+            if (whole) {
+                const d2u v = *(const gd2u*)(pa + kk);
+                v0 = v[0];
+                v1 = v[1];
+            } else {
+                v0 = pa[kc0];
+                v1 = pa[kc1];
+            }
+            a[2 * q] = (ok0 && vi) ? v0 : 0.0;
+            a[2 * q + 1] = (ok1 && vi) ? v1 : 0.0;
+#pragma unroll
+            for (int j = 0; j < NB; ++j) {
+                const double w0 = pb[j][(int64_t)kc0 * lcap], w1 = pb[j][(int64_t)kc1 * lcap];
+                b[2 * q][j] = (ok0 && vb[j]) ? w0 : 0.0;
+                b[2 * q + 1][j] = (ok1 && vb[j]) ? w1 : 0.0;
+            }
+        }
+        if (ki == kit - 1) {  // uniform: the block's Omega entries for its fold
+#pragma unroll
+            for (int j = 0; j < NB; ++j)
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
-                    const int ii = m0 + 16 * w + lg + 4 * v, c = n0 + 16 * j + li;
-                    const double o = gptr(Om)[(int64_t)min(ii, n - 1) * lcap + min(c, nc - 1)];
-                    part[j] += ((ii < n && c < nc) ? o : 0.0) * acc[j][v];
+                    const int ii = 16 * bk + lg + 4 * v, c = 16 * j + li;
+                    const double om = gptr(Om)[(int64_t)min(ii, n - 1) * lcap + min(c, nc - 1)];
+                    o[j][v] = (ii < n && c < nc) ? om : 0.0;
                 }
         }
-        ldouble* red = lds;  // 4 x tw partial sums (the staging area is idle here)
+    };
+    double4_t acc[NB];
+    double part[NB];
 #pragma unroll
-        for (int j = 0; j < TN; ++j) {
-            double s = part[j];
-            s += __shfl_xor(s, 16, 64);
-            s += __shfl_xor(s, 32, 64);
-            if (lg == 0) red[w * tw + 16 * j + li] = s;
+    for (int j = 0; j < NB; ++j) {
+        acc[j] = double4_t{0.0, 0.0, 0.0, 0.0};
+        part[j] = 0.0;
+    }
+    auto mma = [&](const StageA& a, const StageB& b) {
+#pragma unroll
+        for (int s2 = 0; s2 < KS; ++s2)
+#pragma unroll
+            for (int j = 0; j < NB; ++j) acc[j] = mfma_f64_16x16x4(a[s2], b[s2][j], acc[j]);
+    };
+    // after step st: fold a finished block, store a finished row
+    auto after = [&](int st, const StageO& o) {
+        const int rem = st % per_row;
+        if ((rem + 1) % kit != 0) return;  // uniform
+#pragma unroll
+        for (int j = 0; j < NB; ++j) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) part[j] += o[j][v] * acc[j][v];
+            acc[j] = double4_t{0.0, 0.0, 0.0, 0.0};
         }
-        __syncthreads();
-        for (int c = tid; c < tw; c += 256)
-            if (n0 + c < nc) gptr(out)[n0 + c] = ((red[c] + red[tw + c]) + red[2 * tw + c]) + red[3 * tw + c];
-        __syncthreads();
+        if (rem + 1 != per_row) return;  // uniform
+        const int row = a0 + astep * (st / per_row);
+#pragma unroll
+        for (int j = 0; j < NB; ++j) {
+            double sj = part[j];
+            sj += __shfl_xor(sj, 16, 64);
+            sj += __shfl_xor(sj, 32, 64);
+            if (lg == 0 && vb[j]) gptr(W)[(int64_t)row * lcap + 16 * j + li] = sj;
+            part[j] = 0.0;
+        }
+    };
+    StageA sa0, sa1;
+    StageB sb0, sb1;
+    StageO so0, so1;
+    load(0, sa0, sb0, so0);
+    for (int st = 0; st < steps; st += 2) {  // uniform per wave
+        const bool more1 = st + 1 < steps, more2 = st + 2 < steps;
+        if (more1) load(st + 1, sa1, sb1, so1);
+        mma(sa0, sb0);
+        after(st, so0);
+        if (more2) load(st + 2, sa0, sb0, so0);
+        if (more1) {
+            mma(sa1, sb1);
+            after(st + 1, so1);
+        }
     }
 }
 
@@ -1004,16 +1085,18 @@ __device__ __noinline__ void pc_core(const BatchTT* t, int m, int k, int c0, int
         return;
     }
     const double* Wn = t->w + t->woff[k + 1] + c0;
-    for (int a = m; a < r0; a += t->T) {
-        const double* Xa = X + (int64_t)a * n * r1;
-        double* out = W + (int64_t)a * lcap;
-        if (nc <= 16)
-            pc_row<1>(Xa, n, r1, Wn, lcap, Om, nc, out, lds);
-        else if (nc <= 32)
-            pc_row<2>(Xa, n, r1, Wn, lcap, Om, nc, out, lds);
+    // rows a = m + T (w + 4 u) for wave w of member m, 64 columns at a time
+    const int a0 = m + t->T * wave_id(), astep = 4 * t->T;
+    for (int n0 = 0; n0 < nc; n0 += 64) {
+        const int nb = min(64, nc - n0);
+        if (nb <= 16)
+            pc_stream<1, 8>(X, r0, n, r1, Wn + n0, lcap, Om + n0, nb, W + n0, a0, astep);
+        else if (nb <= 32)
+            pc_stream<2, 8>(X, r0, n, r1, Wn + n0, lcap, Om + n0, nb, W + n0, a0, astep);
         else
-            pc_row<4>(Xa, n, r1, Wn, lcap, Om, nc, out, lds);
+            pc_stream<4, 4>(X, r0, n, r1, Wn + n0, lcap, Om + n0, nb, W + n0, a0, astep);
     }
+    __syncthreads();
 }
 
 // One right-to-left pass: Omega and W for columns [c0, c0+nc) of modes k1..d.
@@ -1059,26 +1142,39 @@ __device__ __noinline__ int project_and_next(const BatchTT* t, int m, int par, i
     double* Q = t->q;
     atb(Q, rows, 1, lk, ycur, R, 1, R, rb, re, slot_of(t, par, m), lds);
     // this member's rows of Q (column-major) into the output core
-    // (row-major), through LDS in 64 x 32 tiles so that both the reads and
-    // the writes are contiguous
+    // (row-major), through LDS in 64 x 64 tiles so that both the reads and
+    // the writes are contiguous; the next tile's reads are in flight while
+    // the current one is written
     gdouble* Yk = gptr(t->Y[k - 1]);
     const gdouble* Qg = gptr(Q);
-    for (int r0 = rb; r0 < re; r0 += 64)
-        for (int c0 = 0; c0 < lk; c0 += 32) {
-            const int nr = min(64, re - r0), ncc = min(32, lk - c0);
+    {
+        const int nct = (lk + 63) / 64, ntile = ((re - rb + 63) / 64) * nct;
+        double buf[16];
+        auto read_tile = [&](int tile) {  // thread -> row tid % 64, column tid / 64 + 4 u
+            const int r0 = rb + (tile / nct) * 64, c0 = (tile % nct) * 64;
+            const int r = min(r0 + (int)(threadIdx.x & 63), re - 1);
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {  // read: thread -> row tid % 64, column tid / 64 + 4 u
-                const int r = threadIdx.x & 63, c = (threadIdx.x >> 6) + 4 * u;
-                if (r < nr && c < ncc) lds[c * 65 + r] = Qg[(int64_t)(c0 + c) * rows + r0 + r];
+            for (int u = 0; u < 16; ++u) {
+                const int c = min(c0 + (int)(threadIdx.x >> 6) + 4 * u, lk - 1);
+                buf[u] = Qg[(int64_t)c * rows + r];
             }
-            __syncthreads();
+        };
+        if (ntile > 0 && rb < re) read_tile(0);
+        for (int tile = 0; tile < ntile && rb < re; ++tile) {
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {  // write: thread -> column tid % 32, row tid / 32 + 8 u
-                const int c = threadIdx.x & 31, r = (threadIdx.x >> 5) + 8 * u;
+            for (int u = 0; u < 16; ++u) lds[((threadIdx.x >> 6) + 4 * u) * 65 + (threadIdx.x & 63)] = buf[u];
+            __syncthreads();
+            if (tile + 1 < ntile) read_tile(tile + 1);
+            const int r0 = rb + (tile / nct) * 64, c0 = (tile % nct) * 64;
+            const int nr = min(64, re - r0), ncc = min(64, lk - c0);
+#pragma unroll
+            for (int u = 0; u < 16; ++u) {  // write: thread -> column tid % 64, row tid / 64 + 4 u
+                const int c = threadIdx.x & 63, r = (threadIdx.x >> 6) + 4 * u;
                 if (r < nr && c < ncc) Yk[(int64_t)(r0 + r) * lk + c0 + c] = lds[c * 65 + r];
             }
             __syncthreads();
         }
+    }
     team_sync(*t);
     const int E = lk * R;
     reduce_slots(slots_base(t, par), t->pslot, T, (int)((int64_t)E * m / T), (int)((int64_t)E * (m + 1) / T), R,
