@@ -46,17 +46,19 @@
 namespace ttr {
 namespace {
 
-// LDS (36 KB, below 64 KiB): the b x b Gram / Cholesky factor G, or the
-// double-buffered GEMM slabs (never live at the same time), then misc
-// scratch.
+// LDS (71 KB of the CU's 160 KB; one workgroup per CU): the b x b Gram /
+// Cholesky factor G, or the double-buffered GEMM slabs, or a 64-column
+// block of W_{k+1} (never live at the same time), then misc scratch.
 constexpr int kLD = kBatchMaxBlock + 1;                        // LDS stride of b x b matrices
 constexpr int kSlab = 16;                                      // K depth of a staged GEMM slab
 constexpr int kSP = 68;                                        // LDS stride of a staged slab row
 constexpr int kSlabDoubles = kSlab * kSP;                      // one 64 x 16 panel slab
 constexpr int kStageDoubles = 4 * kSlabDoubles;                // A and B slabs, double-buffered
-constexpr int kMisc = kBatchMaxBlock * kLD > kStageDoubles ? kBatchMaxBlock * kLD : kStageDoubles;
+constexpr int kWRows = 128, kWLD = 68;                          // W_{k+1} column block held in LDS
+constexpr int kWDoubles = kWRows * kWLD;
+constexpr int kMisc = std::max({kBatchMaxBlock * kLD, kStageDoubles, kWDoubles});
 constexpr int kLdsDoubles = kMisc + 2 * kBatchMaxBlock + 16;  // G, misc
-static_assert(kLdsDoubles * 8 + 16 <= 65536, "LDS layout must stay below 64 KiB");
+static_assert(kLdsDoubles * 8 + 16 <= 80 * 1024, "LDS layout must stay below 80 KiB");
 static_assert(4 * 256 <= kMisc, "atb's wave partial tiles must fit below misc");
 constexpr double kUnit = 1.1102230246251565e-16;               // 2^-53
 constexpr uint64_t kSpinTicks = 500000000ull;                  // 5 s of the 100 MHz wall clock
@@ -455,7 +457,7 @@ __device__ __noinline__ void gemm_rows(const double* A, int64_t ars, int64_t acs
     else if (N <= 32)
         rows_stream<2, 4>(A, ars, acs, B, brs, bcs, C, crs, ccs, rb, re, N, K, alpha, beta);
     else
-        rows_stream<4, 2>(A, ars, acs, B, brs, bcs, C, crs, ccs, rb, re, N, K, alpha, beta);
+        rows_stream<4, 4>(A, ars, acs, B, brs, bcs, C, crs, ccs, rb, re, N, K, alpha, beta);
 }
 
 // gemm_rows that also writes this member's partial Gram matrix of the
@@ -963,7 +965,8 @@ __device__ __noinline__ void gen_omega(const BatchTT* t, int m, int j0, int c0, 
 // paired as in atb_stream (16-byte loads of a core row).
 template <int NB, int KS>
 __device__ __forceinline__ void pc_stream(const double* X, int r0, int n, int r1, const double* Wn, int lcap,
-                                          const double* Om, int nc, double* W, int a0, int astep) {
+                                          const double* Om, int nc, double* W, int a0, int astep,
+                                          const ldouble* wl) {
     static_assert(KS % 2 == 0, "K steps come in pairs");
     const int l = lane_id(), li = l & 15, lg = l >> 4;
     const int nrow = a0 < r0 ? (r0 - a0 + astep - 1) / astep : 0;
@@ -1004,7 +1007,14 @@ __device__ __forceinline__ void pc_stream(const double* X, int r0, int n, int r1
             a[2 * q + 1] = (ok1 && vi) ? v1 : 0.0;
 #pragma unroll
             for (int j = 0; j < NB; ++j) {
-                const double w0 = pb[j][(int64_t)kc0 * lcap], w1 = pb[j][(int64_t)kc1 * lcap];
+                double w0, w1;
+                if (wl) {  // uniform: W_{k+1}'s block staged in LDS
+                    w0 = wl[kc0 * kWLD + 16 * j + li];
+                    w1 = wl[kc1 * kWLD + 16 * j + li];
+                } else {
+                    w0 = pb[j][(int64_t)kc0 * lcap];
+                    w1 = pb[j][(int64_t)kc1 * lcap];
+                }
                 b[2 * q][j] = (ok0 && vb[j]) ? w0 : 0.0;
                 b[2 * q + 1][j] = (ok1 && vb[j]) ? w1 : 0.0;
             }
@@ -1085,18 +1095,30 @@ __device__ __noinline__ void pc_core(const BatchTT* t, int m, int k, int c0, int
         return;
     }
     const double* Wn = t->w + t->woff[k + 1] + c0;
-    // rows a = m + T (w + 4 u) for wave w of member m, 64 columns at a time
+    // rows a = m + T (w + 4 u) for wave w of member m, 64 columns at a time;
+    // with r1 <= kWRows the block of W_{k+1} is staged in LDS first (every
+    // row of the core multiplies all of it)
     const int a0 = m + t->T * wave_id(), astep = 4 * t->T;
+    const bool staged = r1 <= kWRows;
     for (int n0 = 0; n0 < nc; n0 += 64) {
         const int nb = min(64, nc - n0);
+        if (staged) {
+            const gdouble* wg = gptr(Wn) + n0;
+            for (int e = threadIdx.x; e < r1 * 64; e += 256) {
+                const int kq = e >> 6, c = e & 63;
+                lds[kq * kWLD + c] = c < nb ? wg[(int64_t)kq * lcap + c] : 0.0;
+            }
+            __syncthreads();
+        }
+        const ldouble* wl = staged ? lds : nullptr;
         if (nb <= 16)
-            pc_stream<1, 8>(X, r0, n, r1, Wn + n0, lcap, Om + n0, nb, W + n0, a0, astep);
+            pc_stream<1, 8>(X, r0, n, r1, Wn + n0, lcap, Om + n0, nb, W + n0, a0, astep, wl);
         else if (nb <= 32)
-            pc_stream<2, 8>(X, r0, n, r1, Wn + n0, lcap, Om + n0, nb, W + n0, a0, astep);
+            pc_stream<2, 8>(X, r0, n, r1, Wn + n0, lcap, Om + n0, nb, W + n0, a0, astep, wl);
         else
-            pc_stream<4, 4>(X, r0, n, r1, Wn + n0, lcap, Om + n0, nb, W + n0, a0, astep);
+            pc_stream<4, 4>(X, r0, n, r1, Wn + n0, lcap, Om + n0, nb, W + n0, a0, astep, wl);
+        __syncthreads();  // the staged block is replaced by the next one
     }
-    __syncthreads();
 }
 
 // One right-to-left pass: Omega and W for columns [c0, c0+nc) of modes k1..d.
