@@ -315,10 +315,21 @@ struct GramAcc {
     double4_t g[NB * (NB + 1) / 2];
 };
 
+// B(k, c) (K <= kWRows, N <= 64) into LDS at k kWLD + c, zero past N; every
+// thread of the workgroup calls it, and a barrier must follow.
+__device__ __forceinline__ void stage_b(const double* B, int64_t brs, int64_t bcs, int K, int N, ldouble* lds) {
+    const gdouble* g = gptr(B);
+    for (int e = threadIdx.x; e < K * 64; e += 256) {
+        const int k = e >> 6, c = e & 63;
+        lds[k * kWLD + c] = c < N ? g[(int64_t)k * brs + (int64_t)c * bcs] : 0.0;
+    }
+}
+
 template <int NB, int KS, bool GRAM = false>
 __device__ __forceinline__ void rows_stream(const double* A, int64_t ars, int64_t acs, const double* B, int64_t brs,
                                             int64_t bcs, double* C, int64_t crs, int64_t ccs, int rb, int re, int N,
-                                            int K, double alpha, double beta, GramAcc<NB>* gram = nullptr) {
+                                            int K, double alpha, double beta, const ldouble* wl,
+                                            GramAcc<NB>* gram = nullptr) {
     // This wave's 16-row blocks r0 = rb + 16 w + 64 u in turn; each block's
     // K range in steps of 4 KS.  The (block, step) sequence runs through two
     // register stages, so the loads of the next step (possibly the next
@@ -381,7 +392,14 @@ __device__ __forceinline__ void rows_stream(const double* A, int64_t ars, int64_
             a[2 * q + 1] = (ok1 && vr) ? v1 : 0.0;
 #pragma unroll
             for (int j = 0; j < NB; ++j) {
-                const double u0 = pb[j][kc0 * brs], u1 = pb[j][kc1 * brs];
+                double u0, u1;
+                if (wl) {  // uniform: B staged in LDS
+                    u0 = wl[kc0 * kWLD + 16 * j + li];
+                    u1 = wl[kc1 * kWLD + 16 * j + li];
+                } else {
+                    u0 = pb[j][kc0 * brs];
+                    u1 = pb[j][kc1 * brs];
+                }
                 b[2 * q][j] = (ok0 && vb[j]) ? u0 : 0.0;
                 b[2 * q + 1][j] = (ok1 && vb[j]) ? u1 : 0.0;
             }
@@ -448,16 +466,23 @@ __device__ __forceinline__ void rows_stream(const double* A, int64_t ars, int64_
 __device__ __noinline__ void gemm_rows(const double* A, int64_t ars, int64_t acs, const double* B, int64_t brs,
                                        int64_t bcs, double* C, int64_t crs, int64_t ccs, int rb, int re, int N, int K,
                                        double alpha, double beta, ldouble* lds) {
-    (void)lds;
     if (re <= rb || N <= 0) return;
+    // B (at most kWRows x 64) is read by every row block: staged in LDS
+    const bool staged = K <= kWRows && N <= 64;
+    if (staged) {
+        stage_b(B, brs, bcs, K, N, lds);
+        __syncthreads();
+    }
+    const ldouble* wl = staged ? lds : nullptr;
     if (N <= 16 && K <= 16)  // one 16-deep step per block
-        rows_stream<1, 4>(A, ars, acs, B, brs, bcs, C, crs, ccs, rb, re, N, K, alpha, beta);
+        rows_stream<1, 4>(A, ars, acs, B, brs, bcs, C, crs, ccs, rb, re, N, K, alpha, beta, wl);
     else if (N <= 16)
-        rows_stream<1, 8>(A, ars, acs, B, brs, bcs, C, crs, ccs, rb, re, N, K, alpha, beta);
+        rows_stream<1, 8>(A, ars, acs, B, brs, bcs, C, crs, ccs, rb, re, N, K, alpha, beta, wl);
     else if (N <= 32)
-        rows_stream<2, 4>(A, ars, acs, B, brs, bcs, C, crs, ccs, rb, re, N, K, alpha, beta);
+        rows_stream<2, 4>(A, ars, acs, B, brs, bcs, C, crs, ccs, rb, re, N, K, alpha, beta, wl);
     else
-        rows_stream<4, 4>(A, ars, acs, B, brs, bcs, C, crs, ccs, rb, re, N, K, alpha, beta);
+        rows_stream<4, 4>(A, ars, acs, B, brs, bcs, C, crs, ccs, rb, re, N, K, alpha, beta, wl);
+    if (staged) __syncthreads();  // the caller may reuse the LDS
 }
 
 // gemm_rows that also writes this member's partial Gram matrix of the
@@ -473,9 +498,15 @@ __device__ __forceinline__ void gemm_rows_gram_t(const double* A, int64_t ars, i
     GramAcc<NB> ga;
 #pragma unroll
     for (int e = 0; e < NB * (NB + 1) / 2; ++e) ga.g[e] = double4_t{0.0, 0.0, 0.0, 0.0};
-    rows_stream<NB, KS, true>(A, ars, acs, B, brs, bcs, C, crs, ccs, rb, re, N, K, alpha, beta, &ga);
+    const bool staged = K <= kWRows && N <= 64;
+    if (staged) {
+        stage_b(B, brs, bcs, K, N, lds);
+        __syncthreads();
+    }
+    rows_stream<NB, KS, true>(A, ars, acs, B, brs, bcs, C, crs, ccs, rb, re, N, K, alpha, beta,
+                              staged ? lds : nullptr, &ga);
     const int l = lane_id(), li = l & 15, lg = l >> 4, w = wave_id(), tid = threadIdx.x;
-    __syncthreads();  // the caller's LDS contents (a factor being read) are no longer needed
+    __syncthreads();  // the staged B and the caller's LDS contents are no longer needed
     int e = 0;
 #pragma unroll
     for (int j1 = 0; j1 < NB; ++j1)
