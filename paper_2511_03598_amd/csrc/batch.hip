@@ -325,7 +325,7 @@ __device__ __forceinline__ void stage_b(const double* B, int64_t brs, int64_t bc
     }
 }
 
-template <int NB, int KS, bool GRAM = false>
+template <int NB, int KS, bool LB, bool GRAM = false>
 __device__ __forceinline__ void rows_stream(const double* A, int64_t ars, int64_t acs, const double* B, int64_t brs,
                                             int64_t bcs, double* C, int64_t crs, int64_t ccs, int rb, int re, int N,
                                             int K, double alpha, double beta, const ldouble* wl,
@@ -390,29 +390,47 @@ __device__ __forceinline__ void rows_stream(const double* A, int64_t ars, int64_
             }
             a[2 * q] = (ok0 && vr) ? v0 : 0.0;
             a[2 * q + 1] = (ok1 && vr) ? v1 : 0.0;
+            if (!LB) {
 #pragma unroll
-            for (int j = 0; j < NB; ++j) {
-                double u0, u1;
-                if (wl) {  // uniform: B staged in LDS
-                    u0 = wl[kc0 * kWLD + 16 * j + li];
-                    u1 = wl[kc1 * kWLD + 16 * j + li];
-                } else {
-                    u0 = pb[j][kc0 * brs];
-                    u1 = pb[j][kc1 * brs];
+                for (int j = 0; j < NB; ++j) {
+                    const double u0 = pb[j][kc0 * brs], u1 = pb[j][kc1 * brs];
+                    b[2 * q][j] = (ok0 && vb[j]) ? u0 : 0.0;
+                    b[2 * q + 1][j] = (ok1 && vb[j]) ? u1 : 0.0;
                 }
-                b[2 * q][j] = (ok0 && vb[j]) ? u0 : 0.0;
-                b[2 * q + 1][j] = (ok1 && vb[j]) ? u1 : 0.0;
             }
         }
     };
     double4_t acc[NB];
 #pragma unroll
     for (int j = 0; j < NB; ++j) acc[j] = double4_t{0.0, 0.0, 0.0, 0.0};
-    auto mma = [&](const StageA& a, const StageB& b) {
+    // with B staged in LDS (LB) its entries are read just before their
+    // MFMAs, so a register stage holds only A's rows
+    auto mma = [&](int st, const StageA& a, const StageB& b) {
+        if (LB) {
+            const int k = (st % kit) * 4 * KS;
 #pragma unroll
-        for (int s = 0; s < KS; ++s)
+            for (int q = 0; q < KS / 2; ++q) {
+                const int kk = k + 8 * q + 2 * lg;
+                const bool ok0 = kk < K, ok1 = kk + 1 < K;
+                const int kc0 = min(kk, K - 1), kc1 = min(kk + 1, K - 1);
+                double u0[NB], u1[NB];
 #pragma unroll
-            for (int j = 0; j < NB; ++j) acc[j] = mfma_f64_16x16x4(a[s], b[s][j], acc[j]);
+                for (int j = 0; j < NB; ++j) {
+                    const double w0 = wl[kc0 * kWLD + 16 * j + li], w1 = wl[kc1 * kWLD + 16 * j + li];
+                    u0[j] = (ok0 && vb[j]) ? w0 : 0.0;
+                    u1[j] = (ok1 && vb[j]) ? w1 : 0.0;
+                }
+#pragma unroll
+                for (int j = 0; j < NB; ++j) acc[j] = mfma_f64_16x16x4(a[2 * q], u0[j], acc[j]);
+#pragma unroll
+                for (int j = 0; j < NB; ++j) acc[j] = mfma_f64_16x16x4(a[2 * q + 1], u1[j], acc[j]);
+            }
+        } else {
+#pragma unroll
+            for (int s2 = 0; s2 < KS; ++s2)
+#pragma unroll
+                for (int j = 0; j < NB; ++j) acc[j] = mfma_f64_16x16x4(a[s2], b[s2][j], acc[j]);
+        }
     };
     // after the last step of a block: its stores (and Gram products)
     auto finish = [&](int blk, const StageC& cv) {
@@ -451,11 +469,11 @@ __device__ __forceinline__ void rows_stream(const double* A, int64_t ars, int64_
     for (int st = 0; st < steps; st += 2) {  // uniform per wave
         const bool more1 = st + 1 < steps, more2 = st + 2 < steps;
         if (more1) load(st + 1, a1, b1, c1);
-        mma(a0, b0);
+        mma(st, a0, b0);
         if ((st + 1) % kit == 0) finish(st / kit, c0);
         if (more2) load(st + 2, a0, b0, c0);
         if (more1) {
-            mma(a1, b1);
+            mma(st + 1, a1, b1);
             if ((st + 2) % kit == 0) finish((st + 1) / kit, c1);
         }
     }
@@ -473,15 +491,23 @@ __device__ __noinline__ void gemm_rows(const double* A, int64_t ars, int64_t acs
         stage_b(B, brs, bcs, K, N, lds);
         __syncthreads();
     }
-    const ldouble* wl = staged ? lds : nullptr;
-    if (N <= 16 && K <= 16)  // one 16-deep step per block
-        rows_stream<1, 4>(A, ars, acs, B, brs, bcs, C, crs, ccs, rb, re, N, K, alpha, beta, wl);
-    else if (N <= 16)
-        rows_stream<1, 8>(A, ars, acs, B, brs, bcs, C, crs, ccs, rb, re, N, K, alpha, beta, wl);
-    else if (N <= 32)
-        rows_stream<2, 4>(A, ars, acs, B, brs, bcs, C, crs, ccs, rb, re, N, K, alpha, beta, wl);
-    else
-        rows_stream<4, 4>(A, ars, acs, B, brs, bcs, C, crs, ccs, rb, re, N, K, alpha, beta, wl);
+    if (staged) {
+        if (N <= 16 && K <= 16)  // one 16-deep step per block
+            rows_stream<1, 4, true>(A, ars, acs, B, brs, bcs, C, crs, ccs, rb, re, N, K, alpha, beta, lds);
+        else if (N <= 16)
+            rows_stream<1, 8, true>(A, ars, acs, B, brs, bcs, C, crs, ccs, rb, re, N, K, alpha, beta, lds);
+        else if (N <= 32)
+            rows_stream<2, 8, true>(A, ars, acs, B, brs, bcs, C, crs, ccs, rb, re, N, K, alpha, beta, lds);
+        else
+            rows_stream<4, 8, true>(A, ars, acs, B, brs, bcs, C, crs, ccs, rb, re, N, K, alpha, beta, lds);
+    } else {
+        if (N <= 16)
+            rows_stream<1, 8, false>(A, ars, acs, B, brs, bcs, C, crs, ccs, rb, re, N, K, alpha, beta, nullptr);
+        else if (N <= 32)
+            rows_stream<2, 4, false>(A, ars, acs, B, brs, bcs, C, crs, ccs, rb, re, N, K, alpha, beta, nullptr);
+        else
+            rows_stream<4, 4, false>(A, ars, acs, B, brs, bcs, C, crs, ccs, rb, re, N, K, alpha, beta, nullptr);
+    }
     if (staged) __syncthreads();  // the caller may reuse the LDS
 }
 
@@ -503,8 +529,11 @@ __device__ __forceinline__ void gemm_rows_gram_t(const double* A, int64_t ars, i
         stage_b(B, brs, bcs, K, N, lds);
         __syncthreads();
     }
-    rows_stream<NB, KS, true>(A, ars, acs, B, brs, bcs, C, crs, ccs, rb, re, N, K, alpha, beta,
-                              staged ? lds : nullptr, &ga);
+    if (staged)
+        rows_stream<NB, KS, true, true>(A, ars, acs, B, brs, bcs, C, crs, ccs, rb, re, N, K, alpha, beta, lds, &ga);
+    else
+        rows_stream<NB, KS, false, true>(A, ars, acs, B, brs, bcs, C, crs, ccs, rb, re, N, K, alpha, beta, nullptr,
+                                         &ga);
     const int l = lane_id(), li = l & 15, lg = l >> 4, w = wave_id(), tid = threadIdx.x;
     __syncthreads();  // the staged B and the caller's LDS contents are no longer needed
     int e = 0;
@@ -994,7 +1023,7 @@ __device__ __noinline__ void gen_omega(const BatchTT* t, int m, int j0, int c0, 
 // register stages, and a block's last step also loads its Omega entries,
 // so no MFMA or fold waits for a load issued just before it.  K steps are
 // paired as in atb_stream (16-byte loads of a core row).
-template <int NB, int KS>
+template <int NB, int KS, bool LB>
 __device__ __forceinline__ void pc_stream(const double* X, int r0, int n, int r1, const double* Wn, int lcap,
                                           const double* Om, int nc, double* W, int a0, int astep,
                                           const ldouble* wl) {
@@ -1036,18 +1065,13 @@ __device__ __forceinline__ void pc_stream(const double* X, int r0, int n, int r1
             }
             a[2 * q] = (ok0 && vi) ? v0 : 0.0;
             a[2 * q + 1] = (ok1 && vi) ? v1 : 0.0;
+            if (!LB) {
 #pragma unroll
-            for (int j = 0; j < NB; ++j) {
-                double w0, w1;
-                if (wl) {  // uniform: W_{k+1}'s block staged in LDS
-                    w0 = wl[kc0 * kWLD + 16 * j + li];
-                    w1 = wl[kc1 * kWLD + 16 * j + li];
-                } else {
-                    w0 = pb[j][(int64_t)kc0 * lcap];
-                    w1 = pb[j][(int64_t)kc1 * lcap];
+                for (int j = 0; j < NB; ++j) {
+                    const double w0 = pb[j][(int64_t)kc0 * lcap], w1 = pb[j][(int64_t)kc1 * lcap];
+                    b[2 * q][j] = (ok0 && vb[j]) ? w0 : 0.0;
+                    b[2 * q + 1][j] = (ok1 && vb[j]) ? w1 : 0.0;
                 }
-                b[2 * q][j] = (ok0 && vb[j]) ? w0 : 0.0;
-                b[2 * q + 1][j] = (ok1 && vb[j]) ? w1 : 0.0;
             }
         }
         if (ki == kit - 1) {  // uniform: the block's Omega entries for its fold
@@ -1068,11 +1092,34 @@ __device__ __forceinline__ void pc_stream(const double* X, int r0, int n, int r1
         acc[j] = double4_t{0.0, 0.0, 0.0, 0.0};
         part[j] = 0.0;
     }
-    auto mma = [&](const StageA& a, const StageB& b) {
+    // with W_{k+1}'s block in LDS (LB) its entries are read just before
+    // their MFMAs, so a register stage holds only the core's rows
+    auto mma = [&](int st, const StageA& a, const StageB& b) {
+        if (LB) {
+            const int k = ((st % per_row) % kit) * 4 * KS;
 #pragma unroll
-        for (int s2 = 0; s2 < KS; ++s2)
+            for (int q = 0; q < KS / 2; ++q) {
+                const int kk = k + 8 * q + 2 * lg;
+                const bool ok0 = kk < r1, ok1 = kk + 1 < r1;
+                const int kc0 = min(kk, r1 - 1), kc1 = min(kk + 1, r1 - 1);
+                double u0[NB], u1[NB];
 #pragma unroll
-            for (int j = 0; j < NB; ++j) acc[j] = mfma_f64_16x16x4(a[s2], b[s2][j], acc[j]);
+                for (int j = 0; j < NB; ++j) {
+                    const double w0 = wl[kc0 * kWLD + 16 * j + li], w1 = wl[kc1 * kWLD + 16 * j + li];
+                    u0[j] = (ok0 && vb[j]) ? w0 : 0.0;
+                    u1[j] = (ok1 && vb[j]) ? w1 : 0.0;
+                }
+#pragma unroll
+                for (int j = 0; j < NB; ++j) acc[j] = mfma_f64_16x16x4(a[2 * q], u0[j], acc[j]);
+#pragma unroll
+                for (int j = 0; j < NB; ++j) acc[j] = mfma_f64_16x16x4(a[2 * q + 1], u1[j], acc[j]);
+            }
+        } else {
+#pragma unroll
+            for (int s2 = 0; s2 < KS; ++s2)
+#pragma unroll
+                for (int j = 0; j < NB; ++j) acc[j] = mfma_f64_16x16x4(a[s2], b[s2][j], acc[j]);
+        }
     };
     // after step st: fold a finished block, store a finished row
     auto after = [&](int st, const StageO& o) {
@@ -1102,11 +1149,11 @@ __device__ __forceinline__ void pc_stream(const double* X, int r0, int n, int r1
     for (int st = 0; st < steps; st += 2) {  // uniform per wave
         const bool more1 = st + 1 < steps, more2 = st + 2 < steps;
         if (more1) load(st + 1, sa1, sb1, so1);
-        mma(sa0, sb0);
+        mma(st, sa0, sb0);
         after(st, so0);
         if (more2) load(st + 2, sa0, sb0, so0);
         if (more1) {
-            mma(sa1, sb1);
+            mma(st + 1, sa1, sb1);
             after(st + 1, so1);
         }
     }
@@ -1141,13 +1188,21 @@ __device__ __noinline__ void pc_core(const BatchTT* t, int m, int k, int c0, int
             }
             __syncthreads();
         }
-        const ldouble* wl = staged ? lds : nullptr;
-        if (nb <= 16)
-            pc_stream<1, 8>(X, r0, n, r1, Wn + n0, lcap, Om + n0, nb, W + n0, a0, astep, wl);
-        else if (nb <= 32)
-            pc_stream<2, 8>(X, r0, n, r1, Wn + n0, lcap, Om + n0, nb, W + n0, a0, astep, wl);
-        else
-            pc_stream<4, 4>(X, r0, n, r1, Wn + n0, lcap, Om + n0, nb, W + n0, a0, astep, wl);
+        if (staged) {
+            if (nb <= 16)
+                pc_stream<1, 8, true>(X, r0, n, r1, Wn + n0, lcap, Om + n0, nb, W + n0, a0, astep, lds);
+            else if (nb <= 32)
+                pc_stream<2, 8, true>(X, r0, n, r1, Wn + n0, lcap, Om + n0, nb, W + n0, a0, astep, lds);
+            else
+                pc_stream<4, 8, true>(X, r0, n, r1, Wn + n0, lcap, Om + n0, nb, W + n0, a0, astep, lds);
+        } else {
+            if (nb <= 16)
+                pc_stream<1, 8, false>(X, r0, n, r1, Wn + n0, lcap, Om + n0, nb, W + n0, a0, astep, nullptr);
+            else if (nb <= 32)
+                pc_stream<2, 8, false>(X, r0, n, r1, Wn + n0, lcap, Om + n0, nb, W + n0, a0, astep, nullptr);
+            else
+                pc_stream<4, 4, false>(X, r0, n, r1, Wn + n0, lcap, Om + n0, nb, W + n0, a0, astep, nullptr);
+        }
         __syncthreads();  // the staged block is replaced by the next one
     }
 }
