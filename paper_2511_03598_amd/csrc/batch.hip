@@ -788,23 +788,28 @@ __device__ __forceinline__ bool chol_lds(ldouble* G, int b, double shift, bool c
 }
 
 // X = R^{-1} (upper triangular) by back substitution, one column per
-// thread, written straight to dst (b x b row-major, zeros below the
-// diagonal; each thread reads back only its own column).
-__device__ __forceinline__ void rinv_lds(const ldouble* G, int b, double* dst) {
+// thread, in LDS after G (the chain of each column reads only LDS), then
+// copied to dst (b x b row-major, zeros below the diagonal).
+__device__ __forceinline__ void rinv_lds(ldouble* G, int b, double* dst) {
     const int tid = threadIdx.x;
-    for (int e = tid; e < b * b; e += 256)
-        if (e / b > e % b) dst[e] = 0.0;
+    ldouble* X = G + kBatchMaxBlock * kLD;
     if (tid < b) {
         const int c = tid;
-        dst[c * b + c] = 1.0 / G[c * kLD + c];
+        X[c * kLD + c] = 1.0 / G[c * kLD + c];
         for (int i = c - 1; i >= 0; --i) {
             double s = 0.0;
-            for (int k = i + 1; k <= c; ++k) s += G[i * kLD + k] * dst[k * b + c];
-            dst[i * b + c] = -s / G[i * kLD + i];
+            for (int k = i + 1; k <= c; ++k) s += G[i * kLD + k] * X[k * kLD + c];
+            X[i * kLD + c] = -s / G[i * kLD + i];
         }
     }
     __syncthreads();
+    for (int e = tid; e < b * b; e += 256) {
+        const int i = e / b, c = e - i * b;
+        gptr(dst)[e] = i > c ? 0.0 : X[i * kLD + c];
+    }
+    __syncthreads();
 }
+static_assert(2 * kBatchMaxBlock * kLD <= kMisc, "R^{-1} must fit between G and the misc area");
 
 // Householder QR of a rows x b column-major panel by one workgroup,
 // overwritten by the explicit Q with diag(R) >= 0; V (rows x b) holds the
