@@ -1249,6 +1249,104 @@ __device__ __noinline__ int norm_estimate(const BatchTT* t, int m, int par, doub
 // Projection M = Q^T V(Y_k) (lk x R) reduced over the team by entry
 // ranges, this member's rows of the output core V(Y_k) <- Q, and the next
 // core H(Y_{k+1}) = M H(X_{k+1}) (lk x n_{k+1} r_{k+1}) by output tiles.
+// C[0:Mg, cb:ce] = A B for A (Mg <= 64 rows, K <= kWRows) staged in LDS as
+// Al[k kWLD + m] (rows past Mg zero) and B (K x ncols, row stride ldb)
+// streamed from global memory: wave w takes the 16-column blocks cb +
+// 16 (w + 4 u) < ce, each over K in steps of 4 KS, the (block, step)
+// sequence through two register stages of B values.  The MFMA order per
+// output tile is that of a K loop in steps of 4, as in wg_tile.
+template <int MB, int KS>
+__device__ __forceinline__ void cols_stream(const ldouble* Al, int Mg, int K, const double* B, int64_t ldb, double* C,
+                                            int64_t ldc, int cb, int ce) {
+    const int l = lane_id(), li = l & 15, lg = l >> 4;
+    const int cfirst = cb + 16 * wave_id();
+    const int kit = (K + 4 * KS - 1) / (4 * KS);
+    const int nblk = cfirst < ce ? (ce - cfirst + 63) / 64 : 0;
+    const int steps = nblk * kit;
+    if (steps == 0) return;
+    typedef double StageB[KS];
+    auto load = [&](int st, StageB& b) {
+        const int blk = st / kit, k = (st - blk * kit) * 4 * KS;
+        const int c = cfirst + 64 * blk + li;
+        const bool vc = c < ce;
+        const gdouble* pb = gptr(B) + min(c, ce - 1);
+#pragma unroll
+        for (int s2 = 0; s2 < KS; ++s2) {
+            const int kk = k + 4 * s2 + lg;
+            const double v = pb[(int64_t)min(kk, K - 1) * ldb];
+            b[s2] = (kk < K && vc) ? v : 0.0;
+        }
+    };
+    double4_t acc[MB];
+#pragma unroll
+    for (int i = 0; i < MB; ++i) acc[i] = double4_t{0.0, 0.0, 0.0, 0.0};
+    auto mma = [&](int st, const StageB& b) {
+        const int k = (st % kit) * 4 * KS;
+#pragma unroll
+        for (int s2 = 0; s2 < KS; ++s2) {
+            const int kc = min(k + 4 * s2 + lg, K - 1);
+#pragma unroll
+            for (int i = 0; i < MB; ++i) acc[i] = mfma_f64_16x16x4(Al[kc * kWLD + 16 * i + li], b[s2], acc[i]);
+        }
+    };
+    auto finish = [&](int blk) {
+        const int c = cfirst + 64 * blk + li;
+#pragma unroll
+        for (int i = 0; i < MB; ++i) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int r = 16 * i + lg + 4 * v;
+                if (r < Mg && c < ce) gptr(C)[(int64_t)r * ldc + c] = acc[i][v];
+            }
+            acc[i] = double4_t{0.0, 0.0, 0.0, 0.0};
+        }
+    };
+    StageB b0, b1;
+    load(0, b0);
+    for (int st = 0; st < steps; st += 2) {  // uniform per wave
+        const bool more1 = st + 1 < steps, more2 = st + 2 < steps;
+        if (more1) load(st + 1, b1);
+        mma(st, b0);
+        if ((st + 1) % kit == 0) finish(st / kit);
+        if (more2) load(st + 2, b0);
+        if (more1) {
+            mma(st + 1, b1);
+            if ((st + 2) % kit == 0) finish((st + 1) / kit);
+        }
+    }
+}
+
+// dst (lk x ncols, row-major) = M (lk x R, row-major) X (R x ncols, row
+// stride ncols) for this member's share of the columns: 64 rows of M at a
+// time staged in LDS (R <= kWRows), X streamed (cols_stream); larger R
+// goes through the LDS-staged tiles of wg_gemm.
+__device__ __noinline__ void next_core(const double* M, int lk, int R, const double* X, int ncols, double* dst, int m,
+                                       int T, ldouble* lds) {
+    if (R > kWRows) {
+        wg_gemm(M, R, 1, X, ncols, 1, dst, ncols, 1, 0, lk, ncols, R, 1.0, 0.0, m, T, lds);
+        return;
+    }
+    int cb, ce;
+    member_rows(ncols, T, m, cb, ce);
+    const gdouble* Mg = gptr(M);
+    for (int m0 = 0; m0 < lk; m0 += 64) {
+        const int rows = min(64, lk - m0);
+        for (int e = threadIdx.x; e < R * 64; e += 256) {
+            const int kq = e >> 6, r = e & 63;
+            lds[kq * kWLD + r] = r < rows ? Mg[(int64_t)(m0 + r) * R + kq] : 0.0;
+        }
+        __syncthreads();
+        double* C = dst + (int64_t)m0 * ncols;
+        if (rows <= 16)
+            cols_stream<1, 8>(lds, rows, R, X, ncols, C, ncols, cb, ce);
+        else if (rows <= 32)
+            cols_stream<2, 8>(lds, rows, R, X, ncols, C, ncols, cb, ce);
+        else
+            cols_stream<4, 8>(lds, rows, R, X, ncols, C, ncols, cb, ce);
+        __syncthreads();  // the staged rows are replaced by the next ones
+    }
+}
+
 __device__ __noinline__ int project_and_next(const BatchTT* t, int m, int par, int k, const double* ycur, int rows,
                                              int R, int lk, int rb, int re, double* dst, ldouble* lds) {
     const int T = t->T;
@@ -1295,7 +1393,7 @@ __device__ __noinline__ int project_and_next(const BatchTT* t, int m, int par, i
     par ^= 1;
     team_sync(*t);
     const int nr1 = (int)(t->n[k] * t->r[k + 1]);
-    wg_gemm(t->m, R, 1, t->X[k], nr1, 1, dst, nr1, 1, 0, lk, nr1, R, 1.0, 0.0, m, T, lds);
+    next_core(t->m, lk, R, t->X[k], nr1, dst, m, T, lds);
     team_sync(*t);
     return par;
 }
