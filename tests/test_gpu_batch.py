@@ -90,6 +90,31 @@ def test_batch_c4_sample_vs_plain_and_oracle(lib):
         _check_vs_oracle(xs[j], to_host(res[j][0]), res[j][1], 1e-6, 16, seeds[j])
 
 
+def test_batch_ranks_above_128_vs_oracle(lib):
+    """Formal ranks above 128 take the kernel's unstaged paths: the
+    contraction of a core with r_k > 128, the sketch and the block updates
+    with K > 128, and the next core through the LDS-staged tiles; once
+    alone and once in a team of two (threshold lowered for the test)."""
+    a = ttgen.small_random(31, 4, 12, [12, 70, 12])
+    b = ttgen.small_random(32, 4, 12, [12, 70, 12])
+    x = tt.formal_sum([a, b], [1.0, 1e-3])
+    assert max(tt.ranks_of(x)) > 128
+    say("batch ranks > 128", tt.ranks_of(x))
+    prev = lib.batch_team_flops(0.0)
+    try:
+        for f0 in (1e12, 1e3):
+            lib.batch_team_flops(f0)
+            plan = lib.BatchPlan([to_dev(x)], 1e-8, 16, [11])
+            say("  team", plan.team(0))
+            plan.launch()
+            (y, info), = plan.finish()
+            say("  ranks", info["ranks"])
+            _check_vs_oracle(x, to_host(y), info, 1e-8, 16, 11)
+            assert tt.left_orth_defect(to_host(y)) < 1e-12
+    finally:
+        lib.batch_team_flops(prev if prev > 0 else -1.0)
+
+
 def test_batch_result_independent_of_the_batch(lib):
     """Each tensor's result is bitwise the same alone and in the batch."""
     idx, xs = _c4_sample()
