@@ -25,12 +25,18 @@
 // a wait that times out sets the tensor's status bit and the kernel still
 // ends.
 //
-// Products: tall panels times small matrices (sketches, residual updates,
-// R^{-1} applications) are 16-row MFMA blocks per wave with whole K
-// extents of loads in flight; long-K reductions with small outputs (Gram
-// matrices, Q^T S, the projection) stream K per wave and add the four wave
-// partials in wave order; the next core, the last core's contraction and
-// the partial contractions use 64-row tiles staged through LDS.  The steps
+// Products stream the tall operand straight into MFMA layout, each wave
+// through two register stages (the next step's loads in flight during the
+// current MFMAs), with K steps paired so that an operand contiguous along K
+// is one 16-byte load per lane: tall panels times small matrices
+// (sketches, residual updates, R^{-1} applications) run over 16-row blocks
+// per wave with the small matrix staged in LDS; long-K reductions with
+// small outputs (Gram matrices, Q^T S, the projection) stream K per wave
+// and add the four wave partials in wave order; the partial contractions
+// stream (row, 16-row block, K step) per wave with W_{k+1}'s column block
+// in LDS; the next core streams the columns of H(X_{k+1}) with 64 rows of
+// the projection in LDS.  The last core's contraction (and products with
+// more than 128 rows of K) use 64 x 64 tiles staged through LDS.  The steps
 // are out-of-line functions so that each gets its own register budget.
 //
 // All reductions run in an order fixed by the tensor's shape and team size,
