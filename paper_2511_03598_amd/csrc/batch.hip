@@ -89,24 +89,32 @@ __device__ __forceinline__ int wave_id() { return threadIdx.x >> 6; }
 // ---------------------------------------------------------------------------
 // Team barrier
 // ---------------------------------------------------------------------------
+// Agent-scope fences on gfx950 act on the whole L2 of the calling XCD (a
+// release writes its dirty lines back, an acquire invalidates it), and that
+// L2 is shared with the other workgroups of the XCD.  So the barrier takes
+// one release fence before arriving and one acquire fence after leaving,
+// and thread 0 polls the generation word with relaxed loads: an acquiring
+// poll would invalidate the L2 once per poll for as long as the member waits.
+// The arrival is a release read-modify-write, which also keeps the read of
+// the old generation before the arrival.
 __device__ __forceinline__ void team_sync(const BatchTT& t) {
     if (t.T == 1) {
         __syncthreads();
         return;
     }
-    __threadfence();
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     __syncthreads();
     if (threadIdx.x == 0 && !(__hip_atomic_load(t.status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & 1)) {
         unsigned* cnt = t.bar;
         unsigned* gen = t.bar + 1;
-        const unsigned g = __hip_atomic_load(gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-        const unsigned arrived = __hip_atomic_fetch_add(cnt, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        const unsigned g = __hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const unsigned arrived = __hip_atomic_fetch_add(cnt, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         if (arrived == (unsigned)t.T - 1u) {
             __hip_atomic_store(cnt, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             __hip_atomic_fetch_add(gen, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         } else {
             const uint64_t t0 = wall_clock64();
-            while (__hip_atomic_load(gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g) {
+            while (__hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == g) {
                 __builtin_amdgcn_s_sleep(2);
                 if (wall_clock64() - t0 > kSpinTicks) {
                     __hip_atomic_fetch_or(t.status, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -116,7 +124,7 @@ __device__ __forceinline__ void team_sync(const BatchTT& t) {
         }
     }
     __syncthreads();
-    __threadfence();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
 }
 
 // Rows [rb, re) of member m of T for a matrix of `rows` rows, in 16-row blocks.
