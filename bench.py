@@ -164,6 +164,8 @@ def main():
                          "rounding of C3 with FP64/FP32/BF16 sketches at tol 1e-4..1e-10; lr: the "
                          "left-to-right partial contractions of C2 (FP64, ell 60)")
     ap.add_argument("--count", type=int, default=256, help="c4: tensors in the batch")
+    ap.add_argument("--team-flops", type=float, default=0.0,
+                    help="c4: use this team threshold instead of autotuning (profiler runs)")
     ap.add_argument("--plain-reps", type=int, default=3, help="c4: repetitions of the plain loop")
     ap.add_argument("--ttsvd-sample", type=int, default=64,
                     help="c4: tensors (systematic sample) rounded by the GPU TT-SVD for its rate")
@@ -241,7 +243,10 @@ def run_headline(args):
     # then the batch laid out once (descriptors uploaded); each step is one
     # persistent launch plus the readback of ranks and run records
     t1 = time.perf_counter()
-    tuned, tune_ms = ttr.batch_autotune(devs, C4_TOL, C4_BLOCK, seeds)
+    if args.team_flops > 0.0:
+        tuned, tune_ms = ttr.batch_team_flops(args.team_flops), {}
+    else:
+        tuned, tune_ms = ttr.batch_autotune(devs, C4_TOL, C4_BLOCK, seeds)
     tune_s = time.perf_counter() - t1
     log("autotune: team threshold %.3g (%s) in %.1f s" % (tuned, tune_ms, tune_s))
     t1 = time.perf_counter()
@@ -329,7 +334,8 @@ def run_headline(args):
                    "ell_block": C4_BLOCK, "sketch_precision": "f64",
                    "input_GB": sum(c.numel() * 8 for x in devs for c in x) / 1e9,
                    "launch": "one persistent kernel per step (graph-capturable), plan built once, "
-                             "team threshold autotuned on the batch beforehand"},
+                             ("team threshold given" if args.team_flops > 0.0 else
+                              "team threshold autotuned on the batch beforehand")},
         "step_s": {"median": pctl(step_s, 50), "p10": pctl(step_s, 10), "p90": pctl(step_s, 90),
                    "steps": args.steps},
         "kernel_ms": {"median": pctl(kern_ms, 50), "p10": pctl(kern_ms, 10), "p90": pctl(kern_ms, 90)},

@@ -505,7 +505,7 @@ def _batch_arrays(obj, tts, tol, seeds, f_init, nrmx, stream):
     obj.seed_arr = (ctypes.c_uint64 * count)(*sds)
 
 
-BATCH_TUNE_CANDIDATES = (3e8, 1e9, 3e9, 1e10, 1e12)
+BATCH_TUNE_CANDIDATES = (3e8, 1e9, 2e9, 2.5e9, 3e9, 1e10, 1e12)
 
 
 def batch_autotune(tts, tol, ell_block, seeds, candidates=BATCH_TUNE_CANDIDATES, f_init=None, stream=None):
