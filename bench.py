@@ -333,7 +333,7 @@ def run_headline(args):
         "config": {"workload": c4_desc(len(xs)), "tensors": len(xs), "tol": C4_TOL,
                    "ell_block": C4_BLOCK, "sketch_precision": "f64",
                    "input_GB": sum(c.numel() * 8 for x in devs for c in x) / 1e9,
-                   "launch": "one persistent kernel per step (graph-capturable), plan built once, "
+                   "launch": "one persistent kernel per step (graph-capturable), plan built once, " +
                              ("team threshold given" if args.team_flops > 0.0 else
                               "team threshold autotuned on the batch beforehand")},
         "step_s": {"median": pctl(step_s, 50), "p10": pctl(step_s, 10), "p90": pctl(step_s, 90),
