@@ -340,7 +340,7 @@ def run_headline(args):
                    "steps": args.steps},
         "kernel_ms": {"median": pctl(kern_ms, 50), "p10": pctl(kern_ms, 10), "p90": pctl(kern_ms, 90)},
         "plan_create_s": plan_s,
-        "autotune": {"team_flops": tuned, "launch_ms": {"%.0e" % k: v for k, v in tune_ms.items()},
+        "autotune": {"team_flops": tuned, "launch_ms": {"%g" % k: v for k, v in tune_ms.items()},
                      "seconds": tune_s,
                      "teams": [int(x) for x in np.bincount([plan.team(i) for i in range(len(xs))])]},
         "batch_call_value": len(xs) / pctl(call_s, 50) if call_s else None,
