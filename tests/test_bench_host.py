@@ -70,3 +70,9 @@ def test_lr_model_counts_each_core_once():
     b, f = bench.lr_model(x, 7)
     assert b == 8 * (6 + 40 + 10) + 8 * 7 * (2 + 5 + 1)
     assert f == 2 * 7 * (6 + 40 + 10)
+
+
+def test_committed_summaries_match_the_sources():
+    # the bench line reports traffic only from counters taken on the current kernel sources
+    assert bench.pmc_traffic(bench.PMC_SUMMARY, bench.PC_SOURCES) is not None
+    assert bench.pmc_traffic(bench.BATCH_PMC_SUMMARY, bench.BATCH_SOURCES) is not None
