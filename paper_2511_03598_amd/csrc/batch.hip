@@ -96,7 +96,10 @@ __device__ __forceinline__ int wave_id() { return threadIdx.x >> 6; }
 // and thread 0 polls the generation word with relaxed loads: an acquiring
 // poll would invalidate the L2 once per poll for as long as the member waits.
 // The arrival is a release read-modify-write, which also keeps the read of
-// the old generation before the arrival.
+// the old generation before the arrival.  Thread 0's own acquire fences
+// complete the chain: the last member to arrive acquires the others'
+// releases on the counter before it releases the generation, and a waiting
+// member acquires that release before the workgroup barrier passes it on.
 __device__ __forceinline__ void team_sync(const BatchTT& t) {
     if (t.T == 1) {
         __syncthreads();
@@ -110,6 +113,7 @@ __device__ __forceinline__ void team_sync(const BatchTT& t) {
         const unsigned g = __hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         const unsigned arrived = __hip_atomic_fetch_add(cnt, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         if (arrived == (unsigned)t.T - 1u) {
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
             __hip_atomic_store(cnt, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             __hip_atomic_fetch_add(gen, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         } else {
@@ -121,6 +125,7 @@ __device__ __forceinline__ void team_sync(const BatchTT& t) {
                     break;
                 }
             }
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         }
     }
     __syncthreads();
