@@ -931,17 +931,20 @@ __device__ __forceinline__ void count_event(const BatchTT* t, int m, int e) {
 // orthonormal to O(u)).  have_gram: every member's
 // partial Gram matrix of S is already in its slot of parity par (written
 // with the block, see gemm_rows_gram); each R^{-1} application that a
-// further pass will factor writes the next Gram the same way.
+// further pass will factor writes the next Gram the same way.  synced: a
+// team barrier has already passed since those slots were written, so the
+// first pass reads them without one.
 __device__ __noinline__ int qr_team(const BatchTT* t, int m, int par, double* S, int rows, int b, int rb, int re,
-                                    ldouble* lds, bool have_gram, int need_ok = 2) {
+                                    ldouble* lds, bool have_gram, int need_ok = 2, bool synced = false) {
     ldouble* G = lds;
     ldouble* misc = lds + kMisc;
     double* rinv = t->priv + (int64_t)m * t->privs;
     int plain_ok = 0, shifts = 0, passes = 0;
     for (;;) {
         if (!have_gram) atb(S, rows, 1, b, S, 1, rows, b, rb, re, slot_of(t, par, m), lds);
+        if (!(have_gram && synced)) team_sync(*t);
         have_gram = false;
-        team_sync(*t);
+        synced = false;
         const double* base = slots_base(t, par);
         par ^= 1;
         reduce_slots(base, t->pslot, t->T, 0, b * b, b, G, kLD);
@@ -1496,7 +1499,8 @@ __device__ __forceinline__ void round_tensor(const BatchTT* t, int m, ldouble* l
                 par ^= 1;  // the block's Gram slots are not consumed
                 break;
             }
-            par = qr_team(t, m, par, S, rows, bb, rb, re, lds, true);
+            // the estimate's barrier in project_out already published the Gram slots
+            par = qr_team(t, m, par, S, rows, bb, rb, re, lds, true, 2, true);
             __syncthreads();
             tock(2);
             par = project_out(t, m, par, Q, rows, ncq, bb, rb, re, 0, &ss, lds);
