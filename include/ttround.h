@@ -341,8 +341,9 @@ void tt_batch_destroy(tt_batch* batch);
  * its layout.
  *
  * tt_batch_autotune: rounds the given batch (arguments as tt_batch_create,
- *   results in ys) once per candidate F0 (after one untimed launch), times
- *   each launch with HIP events on opts->stream into times_ms[j], sets the
+ *   results in ys) three times per candidate F0 (after one untimed launch),
+ *   times each launch with HIP events on opts->stream, stores the median of
+ *   the three in times_ms[j], sets the
  *   current device's F0 to the fastest candidate (*best) and, when the
  *   environment variable TTR_BATCH_TUNE_CACHE names a file, appends
  *   "<gcnArchName>/<compute units> <F0>" to it; the last such line for a

@@ -509,9 +509,9 @@ BATCH_TUNE_CANDIDATES = (3e8, 1e9, 2e9, 2.5e9, 3e9, 1e10, 1e12)
 
 
 def batch_autotune(tts, tol, ell_block, seeds, candidates=BATCH_TUNE_CANDIDATES, f_init=None, stream=None):
-    """Time the persistent batch once per candidate team threshold and make
-    the fastest the device's (tt_batch_autotune).  Returns (best, {candidate:
-    ms})."""
+    """Time the persistent batch three times per candidate team threshold
+    and make the candidate with the fastest median the device's
+    (tt_batch_autotune).  Returns (best, {candidate: median ms})."""
     class _A:
         pass
     a = _A()
