@@ -178,8 +178,8 @@ def main():
                          "reference kernel that scales rocprofv3 FETCH_SIZE/WRITE_SIZE to bytes)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (the design notes "
-              "describe how it would shard); run with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU: the library has no multi-GPU path; run with --gpus 1",
+              file=sys.stderr)
         sys.exit(2)
 
     import torch

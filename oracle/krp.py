@@ -9,8 +9,7 @@ Follows the paper step by step:
     Randomize-then-Orthogonalize with KRP (Sec. 3.3);
   * the norm estimate of Remark 1 and the recompression pass of Remark 2.
 
-Readings taken where the paper is silent or ambiguous (each is listed in the
-design notes of the repository):
+Readings taken where the paper is silent or ambiguous:
   * Index order of the KRP.  The paper writes W_k = H(X_k)[W_{k+1} (.) Omega_k]
     for MATLAB's column-major H.  In row-major storage the column index of
     H(X_k) is i*r_k + b, so the same product is H(X_k)[Omega_k (.) W_{k+1}];

@@ -2,7 +2,7 @@
 
 The paper draws the mode factors Omega_j (n_j x ell) with i.i.d. N(0,1)
 entries (Sec. 2.3, Sec. 3.2, Algorithm "Residual sketching ... using KRPs")
-and uses MATLAB's ``randn``; it fixes no generator.  This build fixes one so
+and uses MATLAB's ``randn``; it fixes no generator.  This library fixes one so
 that the GPU and the oracle draw the same numbers, each side implementing it
 independently from its published definition:
 

@@ -22,8 +22,8 @@ rounded tensor; the two differ by at most tol relative, which does not move
 the bound).  When ranks differ, some adaptive decision sat within the tie
 margin of tau (1e-6 relative; 1e-4 with an FP32 sketch, whose estimates
 differ from the FP64 ones by about 1e-5): both results must then meet the
-tolerance bound (with the 1.5 allowance the design notes give the
-randomized adaptive bound), checked on the dense-free stable norm."""
+tolerance bound, checked on the dense-free stable norm with a factor 1.5:
+the randomized adaptive bound holds with high probability, not surely."""
 import math
 
 import numpy as np

@@ -6,8 +6,7 @@ sum whose ranks add.
 The paper's own workloads (the Matern-kernel TT-cross tensor and the
 TT-GMRES iterates of the parametric "cookie" PDE, Sec. 4.2-4.3) are not
 available; these generators stand in for them with the shapes, ranks and
-value distributions of the synthetic experiment of Sec. 4.1 and of the
-workloads named in the repository's design notes:
+value distributions of the synthetic experiment of Sec. 4.1, at these sizes:
 
   c1   d=6, n=10, X = Z + 0.5 Z - 0.25 Z with Z of ranks 10, N(0,1) cores
        (formal ranks 30, true ranks 10);
